@@ -1,0 +1,227 @@
+"""Pins for the oracle's decompositions, restorations and the FFT translation.
+
+Decompositions are pinned by exact recovery of tensors built with a known
+low-rank structure (non-cubic shapes, so a transposed operand fails), by the
+error bound each algorithm guarantees, by rank-1 special cases, by the
+paper's qualitative invariants (r12 = r34, rank caps), and by Table II.
+The FFT translation is pinned by the plain pairwise sum it must equal.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+def _rand(shape, rng):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def _random_tucker(n, r, rng):
+    C = _rand(r, rng)
+    Us = [_rand((ni, ri), rng) for ni, ri in zip(n, r)]
+    X = np.einsum("abc,xa,yb,zc->xyz", C, *Us) if len(n) == 3 else \
+        np.einsum("abcd,xa,yb,zc,pd->xyzp", C, *Us)
+    return X
+
+
+def test_mode_product_definition():
+    rng = _rng(1)
+    X = _rand((3, 4, 5), rng)
+    U = _rand((6, 4), rng)
+    Y = O.mode_product(X, U, 1)
+    # Eq. (10) written out
+    ref = np.zeros((3, 6, 5), complex)
+    for a in range(3):
+        for v in range(6):
+            for c in range(5):
+                ref[a, v, c] = sum(X[a, i, c] * U[v, i] for i in range(4))
+    np.testing.assert_allclose(Y, ref, rtol=1e-13)
+
+
+def test_truncation_rank_rule():
+    s = np.array([10.0, 3.0, 1.0, 0.1, 0.01])
+    assert O.truncation_rank(s, 0.2) == 3            # tail after 3 = sqrt(0.0101) <= 0.2
+    assert O.truncation_rank(s, 0.1) == 4            # tail after 3 = 0.1005 > 0.1
+    assert O.truncation_rank(s, 0.05) == 4
+    assert O.truncation_rank(s, 0.005) == 5
+    assert O.truncation_rank(s, 0.0) == 5
+    assert O.truncation_rank(s, 1e9) == 1            # rank never drops below 1
+
+
+def test_tucker_recovers_known_ranks_and_restores_exactly():
+    rng = _rng(2)
+    X = _random_tucker((6, 8, 10), (2, 3, 4), rng)
+    C, Us = O.tucker_svd(X, 1e-10)
+    assert C.shape == (2, 3, 4)
+    np.testing.assert_allclose(O.tucker3d_restore_figure3a(C, *Us), X, rtol=0, atol=1e-11 * np.abs(X).max())
+    np.testing.assert_allclose(O.tucker_restore(C, Us), X, rtol=0, atol=1e-11 * np.abs(X).max())
+
+
+def test_tucker_rank_one_separable():
+    rng = _rng(3)
+    a, b, c = _rand(5, rng), _rand(6, rng), _rand(7, rng)
+    X = np.einsum("x,y,z->xyz", a, b, c)
+    C, Us = O.tucker_svd(X, 1e-8)
+    assert C.shape == (1, 1, 1)
+
+
+@pytest.mark.parametrize("gamma", [1e-2, 1e-4])
+def test_tucker_error_bound_on_operator(gamma):
+    _, _, _, Th = O.build_operator((4, 4, 4), 0.5, 2 * math.pi, 5)
+    for p in (0, 17, 40):
+        C, Us = O.tucker_svd(Th[p], gamma)
+        err = np.linalg.norm(O.tucker_restore(C, Us) - Th[p]) / np.linalg.norm(Th[p])
+        assert err <= gamma * (1 + 1e-9)
+        assert max(C.shape) <= 7   # zero slot m = K caps every mode rank at 2K - 1
+
+
+def test_tt_recovers_known_ranks_3d_and_4d():
+    rng = _rng(4)
+    U1, G, U3 = _rand((6, 2), rng), _rand((2, 8, 3), rng), _rand((10, 3), rng)
+    X = np.einsum("xa,ayb,zb->xyz", U1, G, U3)
+    a, cores, b = O.tt_svd(X, 1e-11)
+    assert a.shape == (6, 2) and cores[0].shape == (2, 8, 3) and b.shape == (10, 3)
+    np.testing.assert_allclose(O.tt3d_restore(a, cores[0], b), X, atol=1e-11 * np.abs(X).max())
+    V1, G1, G2, V3 = _rand((5, 2), rng), _rand((2, 6, 4), rng), _rand((4, 7, 3), rng), _rand((9, 3), rng)
+    X4 = np.einsum("xa,ayb,bzc,pc->xyzp", V1, G1, G2, V3)
+    u1, cs, u3 = O.tt_svd(X4, 1e-11)
+    assert u1.shape == (5, 2) and cs[0].shape == (2, 6, 4) and cs[1].shape == (4, 7, 3) and u3.shape == (9, 3)
+    full = O.tt_restore(u1, cs, u3)
+    np.testing.assert_allclose(full, X4, atol=1e-11 * np.abs(X4).max())
+    for p in (0, 4, 8):
+        np.testing.assert_allclose(O.tt4d_restore_direction(u1, cs[0], cs[1], u3, p), X4[..., p],
+                                   atol=1e-11 * np.abs(X4).max())
+
+
+def test_tt_first_rank_not_above_tucker_first_rank():
+    _, _, _, Th = O.build_operator((4, 4, 4), 0.5, 2 * math.pi, 5)
+    for p in (3, 30):
+        Ct, _ = O.tucker_svd(Th[p], 1e-3)
+        u1, _, _ = O.tt_svd(Th[p], 1e-3)
+        assert u1.shape[1] <= Ct.shape[0]
+
+
+def test_htucker_recovers_structure_and_r12_equals_r34():
+    rng = _rng(5)
+    r = (2, 3, 3, 2)
+    n = (5, 6, 7, 8)
+    C12 = _rand((2, 3, 4), rng)
+    C34 = _rand((3, 2, 4), rng)
+    B = _rand((4, 4), rng)
+    Us = [_rand((ni, ri), rng) for ni, ri in zip(n, r)]
+    G = np.einsum("abi,ij,cdj->abcd", C12, B, C34)
+    X = np.einsum("abcd,xa,yb,zc,pd->xyzp", G, *Us)
+    ht = O.htucker_svd(X, 1e-11)
+    r1, r2, r12 = ht["C12"].shape
+    r3, r4, r34 = ht["C34"].shape
+    assert (r1, r2, r3, r4) == r and r12 == r34 == 4
+    full = O.htucker_restore(ht)
+    np.testing.assert_allclose(full, X, atol=1e-10 * np.abs(X).max())
+    for p in (0, 3, 7):
+        Cp = O.htucker_direction_core(ht, p)
+        Tp = O.tucker3d_restore_figure3a(Cp, *ht["U"][:3])
+        np.testing.assert_allclose(Tp, X[..., p], atol=1e-10 * np.abs(X).max())
+
+
+@pytest.mark.parametrize("fmt", ["tucker3d", "tt3d", "tucker4d", "tt4d", "htucker4d"])
+def test_formats_error_bound_and_slices(fmt):
+    """Every format reconstructs the FFT'ed operator within gamma (relative Frobenius, over the
+    whole 3-D or 4-D tensor it compressed), and per-direction restoration equals the slice of the
+    full reconstruction."""
+    _, _, _, Th = O.build_operator((4, 4, 4), 0.5, 2 * math.pi, 5)
+    gamma = 1e-3
+    comp = O.compress(Th, fmt, gamma)
+    R = O.restore_all(comp, Th.shape[0])
+    if fmt.endswith("3d"):
+        for p in range(Th.shape[0]):
+            assert np.linalg.norm(R[p] - Th[p]) <= gamma * np.linalg.norm(Th[p]) * (1 + 1e-9)
+    else:
+        assert np.linalg.norm(R - Th) <= gamma * np.linalg.norm(Th) * (1 + 1e-9)
+    if fmt == "tucker4d":
+        full = O.tucker_restore(comp["C"], comp["U"])
+        np.testing.assert_allclose(np.moveaxis(full, -1, 0), R, atol=1e-12 * np.abs(Th).max())
+    if fmt == "tt4d":
+        full = O.tt_restore(comp["U1"], [comp["C1"], comp["C2"]], comp["U3"])
+        np.testing.assert_allclose(np.moveaxis(full, -1, 0), R, atol=1e-12 * np.abs(Th).max())
+    if fmt == "htucker4d":
+        full = O.htucker_restore(comp)
+        np.testing.assert_allclose(np.moveaxis(full, -1, 0), R, atol=1e-12 * np.abs(Th).max())
+        assert comp["C12"].shape[2] == comp["C34"].shape[2]
+
+
+def test_full_rank_at_zero_tolerance():
+    _, _, _, Th = O.build_operator((4, 4, 4), 0.5, 2 * math.pi, 5)
+    for fmt in ("tucker3d", "tt3d", "tucker4d", "tt4d", "htucker4d"):
+        comp = O.compress(Th, fmt, 0.0)
+        R = O.restore_all(comp, Th.shape[0])
+        assert O.rel_l2(R, Th) < 1e-13, fmt
+
+
+def test_fft_translation_equals_direct_sum():
+    w = synth.TINY
+    _, _, T, Th = O.build_operator(w.K, w.box, w.k, w.L)
+    A = synth.patterns_for(w, nrhs=2)
+    assert O.rel_l2(O.translate_fft(A, Th), O.translate_direct(A, T)) < 1e-13
+
+
+def test_fft_translation_non_cubic_and_delta():
+    K = (3, 5, 4)
+    khat, _ = O.directions(2)
+    T = O.sample_operator(K, 0.5, 2 * math.pi, 2, khat)
+    Th = O.fft_operator(T)
+    A = synth.gaussian_patterns((1, khat.shape[0]) + K, 11)
+    assert O.rel_l2(O.translate_fft(A, Th), O.translate_direct(A, T)) < 1e-13
+    # delta input at v0: B[v'] = T(v' - v0)
+    v0 = (1, 3, 2)
+    D = np.zeros((1, khat.shape[0]) + K, complex)
+    D[0, :, v0[0], v0[1], v0[2]] = 1.0
+    B = O.translate_fft(D, Th)
+    for vp in [(0, 0, 0), (2, 4, 3), (1, 0, 0), (2, 1, 3)]:
+        m = tuple((vp[i] - v0[i]) % (2 * K[i]) for i in range(3))
+        np.testing.assert_allclose(B[0, :, vp[0], vp[1], vp[2]], T[:, m[0], m[1], m[2]], atol=1e-12)
+
+
+def test_compressed_translation_error_within_tolerance():
+    w = synth.TINY
+    _, _, T, Th = O.build_operator(w.K, w.box, w.k, w.L)
+    A = synth.patterns_for(w)
+    exact = O.translate_direct(A, T)
+    for fmt in ("tucker3d", "tt3d", "tucker4d", "tt4d", "htucker4d"):
+        for gamma in (1e-2, 1e-4):
+            comp = O.compress(Th, fmt, gamma)
+            err = O.rel_l2(O.translate_compressed(A, comp), exact)
+            assert err <= 10 * gamma + 1e-6, (fmt, gamma, err)
+
+
+@pytest.mark.slow
+def test_table2_ranks_soft_pin():
+    """Table II, n = 32 column (16^3 boxes, L = 14, 435 directions, gamma = 1e-6).  Readings
+    R1/R4/R6/R9 reproduce the printed ranks within a few units; the direction ranks exactly."""
+    g = json.load(open(os.path.join(GOLD, "table2_ranks.json")))
+    _, _, _, Th = O.build_operator(tuple(g["K"]), 0.5, 2 * math.pi, g["L"], grid="paper")
+    assert Th.shape[0] == 435
+    gamma = g["gamma"]
+    t3 = O.compress(Th, "tucker3d", gamma)
+    assert abs(max(max(r) for r in O.ranks(t3)) - g["tucker3d_rmax"]) <= 2
+    tt3 = O.compress(Th, "tt3d", gamma)
+    assert abs(max(max(r) for r in O.ranks(tt3)) - g["tt3d_rmax"]) <= 2
+    tt4 = O.ranks(O.compress(Th, "tt4d", gamma))
+    assert abs(tt4[0] - g["tt4d_r1"]) <= 2
+    assert abs(tt4[1] - g["tt4d_r2"]) <= 3
+    assert tt4[2] == g["tt4d_r3"]
+    ht = O.ranks(O.compress(Th, "htucker4d", gamma))
+    assert ht[3] == g["htucker_r4"]
+    assert ht[4] == ht[5]
+    assert abs(ht[4] - g["htucker_r12"]) <= 3
+    assert abs(max(ht[:3]) - g["htucker_leaf"]) <= 4
