@@ -1,0 +1,232 @@
+/*
+ * tfmm.h - FFT-based FMM translation with compressed translation operators on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the iterative-solution-stage translation of an
+ * FMM-FFT surface-integral-equation matrix-vector product, Eq. (5) of
+ * Qian & Yucel, "On the Compression of Translation Operator Tensors in
+ * FMM-FFT-Accelerated SIE Simulators via Tensor Decompositions":
+ *
+ *     B_{s,p} = IFFT3( T~_p  .*  FFT3( zero-pad(A_{s,p}) ) )  cropped to the box grid,
+ *
+ * for every plane-wave direction p and right-hand side s, where the FFT'ed
+ * translation operator T~_p (Eq. (7) sampled on the 2Kx x 2Ky x 2Kz box-offset
+ * grid and FFT'ed, Section II-B) is held on the GPU either uncompressed or in one
+ * of the paper's five compressed forms (Tucker-3D/4D, Eqs. (8)-(9); H-Tucker-4D,
+ * Eq. (11); TT-3D/4D, Eqs. (13)-(14)) and restored per direction inside the
+ * translation kernels (Section II-C, Figs. 3-4) without ever being written to
+ * device memory.
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns a tfmm_status; nothing throws across the ABI.
+ *     Arguments are validated before any device work is enqueued.  On error the
+ *     outputs are left untouched, except the B buffer of a translation that
+ *     failed on the device, whose contents are then undefined.
+ *   - Complex numbers are interleaved (re, im) pairs: complex64 = two floats,
+ *     complex128 = two doubles.  Arrays are C order, last index fastest.
+ *   - A tfmm_ctx owns one HIP device, one device-memory budget and one
+ *     scheduler thread.  Calls on one context are serialised by an internal
+ *     mutex and may come from any thread.
+ *   - The library owns operator memory (allocated at setup, charged to the
+ *     context's budget, freed at release).  Callers own A and B.
+ *   - All enqueues are asynchronous with respect to the host: the call returns
+ *     once the work is queued on the given stream.
+ *   - tfmm_last_error() returns a human-readable detail string for the last
+ *     failing call made by the calling thread.
+ */
+#ifndef TFMM_H
+#define TFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tfmm_ctx_s* tfmm_ctx;
+typedef struct tfmm_op_s* tfmm_op;
+typedef uint64_t tfmm_ticket;
+
+typedef enum {
+  TFMM_OK = 0,
+  TFMM_ERR_INVALID_ARG = 1,  /* null pointer, out-of-range size or enum           */
+  TFMM_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement       */
+  TFMM_ERR_BUDGET = 3,       /* the context's device-memory budget is exhausted   */
+  TFMM_ERR_OOM = 4,          /* hipMalloc or host allocation failed               */
+  TFMM_ERR_HIP = 5,          /* a HIP runtime call or kernel launch failed        */
+  TFMM_ERR_BUSY = 6,         /* operator still referenced by queued jobs          */
+  TFMM_ERR_UNKNOWN_TICKET = 7,
+  TFMM_ERR_QUEUE_FULL = 8,
+  TFMM_ERR_INTERNAL = 9,
+  TFMM_ERR_NO_DEVICE = 10    /* no HIP device (the library has no CPU fallback)    */
+} tfmm_status;
+
+/* Operator storage formats (Section II-B). */
+typedef enum {
+  TFMM_FMT_FULL = 0,       /* uncompressed FFT'ed operator, n_dir x n1 x n2 x n3        */
+  TFMM_FMT_TUCKER3D = 1,   /* per direction: core r1 x r2 x r3, factors n_i x r_i, Eq. (8) */
+  TFMM_FMT_TT3D = 2,       /* per direction: U1 n1 x r1, C r1 x n2 x r2, U3 n3 x r2, Eq. (13) */
+  TFMM_FMT_TUCKER4D = 3,   /* one core r1 x r2 x r3 x r4 and four factors, Eq. (9)      */
+  TFMM_FMT_TT4D = 4,       /* U1 n1 x r1, C1 r1 x n2 x r2, C2 r2 x n3 x r3, U3 n_dir x r3, Eq. (14) */
+  TFMM_FMT_HTUCKER4D = 5   /* leaves U1..U4, C12 r1 x r2 x r12, C34 r3 x r4 x r34,
+                              root r12 x r34, Eq. (11), balanced tree {1,2}{3,4}       */
+} tfmm_format;
+
+/* Arithmetic of the restoration contractions (the FFTs and the pointwise
+ * product are always FP32).  BF16X3 splits each FP32 operand into a bf16 high
+ * part and a bf16 remainder and accumulates hi*hi + hi*lo + lo*hi in FP32 on
+ * the matrix cores. */
+typedef enum { TFMM_PREC_FP32 = 0, TFMM_PREC_BF16X3 = 1 } tfmm_precision;
+
+/* Near-field rule (Section II-A): box pairs closer than the rule are handled
+ * classically, so their operator samples are zero.  CHEB: max_i |d_i| <=
+ * near_param (default 1, the 27 nearest boxes).  KAPPA: R < kappa R^s with
+ * kappa = near_param (4 in the paper) and R^s = a sqrt(3)/2. */
+typedef enum { TFMM_NEAR_CHEB = 0, TFMM_NEAR_KAPPA = 1 } tfmm_near_rule;
+
+/* Direction grid (Section II-A, text after Eq. (4)): n_theta Gauss-Legendre
+ * nodes in cos(theta), ascending, times n_phi uniform nodes phi_j = 2 pi j /
+ * n_phi; direction index p = i_theta * n_phi + j_phi. */
+typedef struct {
+  int32_t K[3];            /* box grid Kx, Ky, Kz; each one of 4, 8, 12, 16, 24, 32
+                              (FFT grid n_i = 2 K_i)                                */
+  double box_size;         /* box edge a, in the length unit of 1/k                  */
+  double k;                /* real wavenumber (lossless medium)                       */
+  int32_t L;               /* multipole order; 0 => derive it from `digits`         */
+  double digits;           /* accurate digits, used only when L == 0:
+                              L = ceil(x + 1.8 digits^(2/3) x^(1/3)), x = k a sqrt(3) */
+  int32_t n_theta, n_phi;  /* 0,0 => L+1 and 2(L+1)                                   */
+  tfmm_near_rule near_rule;
+  double near_param;       /* 0 => 1 for CHEB, 4 for KAPPA                            */
+  double scale_re, scale_im; /* global prefactor of Eq. (7); 0,0 => 1                 */
+  tfmm_format fmt;
+  double tol;              /* gamma: relative Frobenius tolerance of the
+                              decomposition (per direction for 3-D formats, over
+                              the whole 4-D tensor otherwise); ignored for FULL   */
+  tfmm_precision prec;
+} tfmm_problem;
+
+typedef struct {
+  tfmm_format fmt;
+  tfmm_precision prec;
+  int32_t K[3], n[3];
+  int32_t n_dir, L;
+  size_t bytes_full;       /* complex64 bytes of the uncompressed operator           */
+  size_t bytes_stored;     /* device bytes of the stored operator                    */
+  size_t elems_stored;     /* complex entries of cores and factors                   */
+  double rel_err_fro;      /* ||T~ - T~hat||_F / ||T~||_F over all directions, FP64 at setup */
+  double max_dir_rel_err;  /* max over directions of the same ratio                  */
+  int32_t ranks[8];        /* format ranks; 3-D formats: maximum over directions     */
+  double setup_seconds;
+} tfmm_op_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` with a device-memory budget for
+ * operators and translation scratch (0 => 90% of the device's free memory).
+ * Fails with TFMM_ERR_NO_DEVICE when no device is visible. */
+tfmm_status tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx* out);
+
+/* Wait for every submitted job, stop the scheduler, free all operators and
+ * scratch.  The handle is invalid afterwards. */
+tfmm_status tfmm_ctx_destroy(tfmm_ctx ctx);
+
+/* Bytes charged to the budget so far and the budget itself. */
+tfmm_status tfmm_ctx_memory(tfmm_ctx ctx, size_t* used, size_t* budget);
+
+/* ---- operator setup (Section II-B; Algorithms 1-3) ------------------------ */
+
+/* Build the FFT'ed translation operator for `prob` and store it in the
+ * requested format: directions and L on the host, Eq. (7) sampled in FP64 on
+ * the device, FFT'ed and compressed in FP64 on the host (truncation: keep the
+ * smallest rank whose discarded singular values have root-sum-square <=
+ * gamma/sqrt(m) ||X||_F, m = d, d-1, 6 for Tucker, TT, H-Tucker), then packed
+ * for the device in the requested precision.  Blocks until the operator is
+ * resident.  TFMM_ERR_BUDGET if it does not fit the remaining budget. */
+tfmm_status tfmm_setup_compressed(tfmm_ctx ctx, const tfmm_problem* prob, tfmm_op* out);
+
+/* Build an operator from caller-supplied factors instead of sampling and
+ * compressing.  `prob` supplies K, the direction count (n_theta * n_phi, or
+ * L-derived), fmt and prec; the physical fields are ignored.  `ranks` and
+ * `data` (complex128, host memory, caller-owned, read during the call only)
+ * are laid out as follows, all arrays C order:
+ *   FULL      ranks: none (nranks 0);  data: T~[n_dir][n1][n2][n3]
+ *   TUCKER3D  ranks: n_dir x {r1,r2,r3}; data per direction p in order:
+ *             C[r1][r2][r3], U1[n1][r1], U2[n2][r2], U3[n3][r3]
+ *   TT3D      ranks: n_dir x {r1,r2};   data per p: U1[n1][r1], C[r1][n2][r2], U3[n3][r2]
+ *   TUCKER4D  ranks: {r1,r2,r3,r4};     data: C[r1][r2][r3][r4], U1, U2, U3, U4[n_dir][r4]
+ *   TT4D      ranks: {r1,r2,r3};        data: U1[n1][r1], C1[r1][n2][r2], C2[r2][n3][r3], U3[n_dir][r3]
+ *   HTUCKER4D ranks: {r1,r2,r3,r4,r12,r34}; data: U1, U2, U3, U4, C12[r1][r2][r12],
+ *             C34[r3][r4][r34], B[r12][r34]
+ * T~_p[x,y,z] is then sum C[a,b,c] U1[x,a] U2[y,b] U3[z,c] (Tucker, with the
+ * 4-D core contracted with row p of U4), sum U1[x,a] C[a,y,b] U3[z,b] (TT-3D),
+ * sum U1[x,a] C1[a,y,b] C2[b,z,c] U3[p,c] (TT-4D), and the Tucker form with core
+ * sum_{b,b'} C12[a1,a2,b] B[b,b'] C34[a3,a4,b'] contracted with row p of U4
+ * (H-Tucker).  `ndata` is the number of doubles in `data`. */
+tfmm_status tfmm_op_import(tfmm_ctx ctx, const tfmm_problem* prob, const int32_t* ranks,
+                           size_t nranks, const double* data, size_t ndata, tfmm_op* out);
+
+tfmm_status tfmm_op_info_get(tfmm_op op, tfmm_op_info* out);
+
+/* Per-direction ranks of a 3-D format (n_dir x 3 for Tucker-3D, n_dir x 2 for
+ * TT-3D) or the format's ranks for 4-D formats.  `need` receives the count. */
+tfmm_status tfmm_op_ranks(tfmm_op op, int32_t* ranks, size_t cap, size_t* need);
+
+/* Copy the operator's factors to host memory in the tfmm_op_import layout
+ * (complex128), for saving and reloading an operator.  With host_buf NULL
+ * only `need` (number of doubles) is returned. */
+tfmm_status tfmm_op_export(tfmm_op op, double* host_buf, size_t cap, size_t* need);
+
+/* Free the operator.  TFMM_ERR_BUSY while submitted jobs still use it. */
+tfmm_status tfmm_op_release(tfmm_ctx ctx, tfmm_op op);
+
+/* ---- translation, Eq. (5) --------------------------------------------------- */
+
+/* Enqueue B = translate(A) for `nrhs` right-hand sides on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  A and B are device pointers to
+ * complex64 arrays [nrhs][n_dir][Kx][Ky][Kz], caller-owned; they must not
+ * alias and must stay valid until the stream reaches the end of the work.
+ * Translation scratch comes from the context (charged to its budget on first
+ * use and kept); concurrent translations on one context are serialised on
+ * scratch by the context mutex and the stream order. */
+tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
+                           void* hip_stream);
+
+/* ---- serving: continuous batching (submit / poll) ------------------------ */
+
+/* Queue a translation job for the context's scheduler thread.  A and B as for
+ * tfmm_translate and caller-owned until the job is reported done.  The job
+ * keeps a reference on `op`.  Jobs that arrive while others run are admitted
+ * as scratch memory frees up and are batched with other jobs on the same
+ * operator.  Returns at once with a ticket. */
+tfmm_status tfmm_submit(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
+                        tfmm_ticket* out);
+
+/* Non-blocking completion check.  done = 1 once B is complete (or the job
+ * failed; then job_status says why).  latency_us = submit-to-completion time. */
+tfmm_status tfmm_poll(tfmm_ctx ctx, tfmm_ticket t, int32_t* done, tfmm_status* job_status,
+                      double* latency_us);
+
+/* Block until the job is done; the ticket is then retired. */
+tfmm_status tfmm_wait(tfmm_ctx ctx, tfmm_ticket t, tfmm_status* job_status, double* latency_us);
+
+/* ---- diagnostics ------------------------------------------------------------ */
+
+const char* tfmm_status_str(tfmm_status s);
+const char* tfmm_last_error(void);
+
+/* Kernel-level timing: when enabled, tfmm_translate brackets each kernel it
+ * launches with HIP events on the launch stream.  tfmm_kernel_times waits for
+ * those events and reports, per kernel name (newline-separated in `names`),
+ * the average duration in ms and the launch count since the last reset; at
+ * most `cap` entries are written, `count` receives the number of names, and a
+ * negative `cap` clears the statistics after reporting. */
+tfmm_status tfmm_set_profiling(tfmm_ctx ctx, int32_t on);
+tfmm_status tfmm_kernel_times(tfmm_ctx ctx, char* names, size_t names_cap, double* avg_ms,
+                              int32_t* launches, int32_t cap, int32_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TFMM_H */

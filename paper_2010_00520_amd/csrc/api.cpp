@@ -1,0 +1,1026 @@
+// C ABI of libtfmm: contexts, operator setup/import/export, translation,
+// kernel timing and the continuous-batching scheduler (include/tfmm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "host_math.h"
+#include "launch.h"
+#include "tfmm.h"
+
+using tfmm::cd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+tfmm_status fail(tfmm_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                               \
+  do {                                                                                              \
+    hipError_t _e = (expr);                                                                         \
+    if (_e != hipSuccess)                                                                           \
+      return fail(TFMM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));                 \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool supported_len(int n) {
+  switch (n) {
+    case 8: case 16: case 24: case 32: case 48: case 64: return true;
+    default: return false;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Objects
+// ---------------------------------------------------------------------------
+
+struct ScratchSlot {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+struct tfmm_op_s {
+  tfmm_ctx ctx = nullptr;
+  tfmm_format fmt = TFMM_FMT_FULL;
+  tfmm_precision prec = TFMM_PREC_FP32;
+  int K[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+  int ndir = 0, L = 0, nq = 0;
+  tfmm::Factors host;                  // complex128 factors (export / import layout)
+  float4* d_full = nullptr;            // FULL operator, [p][n3/2][nq]
+  float2* d_data = nullptr;            // compressed factors, complex64, import layout
+  int* d_desc = nullptr;               // [ndir][8] z-stage descriptors
+  size_t dev_bytes = 0;                // bytes charged to the budget
+  size_t stored_elems = 0;
+  std::vector<int> desc;               // host copy of the descriptors
+  // derived plan
+  int zfmt = 0, cb = 1, KC = 8, lds = 0;
+  size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
+  tfmm_op_info info{};
+  std::atomic<int> refs{0};
+};
+
+struct Job {
+  tfmm_ticket id = 0;
+  tfmm_op op = nullptr;
+  const float2* A = nullptr;
+  float2* B = nullptr;
+  int nrhs = 0;
+  double t_submit = 0.0, t_done = 0.0;
+  std::atomic<int> done{0};
+  tfmm_status status = TFMM_OK;
+};
+
+struct InFlight {
+  hipEvent_t ev = nullptr;
+  std::vector<std::shared_ptr<Job>> jobs;
+  int slot = 0;
+};
+
+struct KernelStat {
+  double total_ms = 0.0;
+  int n = 0;
+};
+
+struct tfmm_ctx_s {
+  int device = 0;
+  size_t budget = 0, used = 0;
+  std::recursive_mutex mu;
+  // translation scratch, one per stream slot (slot 0 = tfmm_translate; 1..S = scheduler streams)
+  static constexpr int kSlots = 3;
+  ScratchSlot scratch[kSlots];
+  std::map<int, float2*> roots;        // n3 -> device table exp(-2 pi i m/n3)
+  // profiling
+  bool prof = false;
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::map<std::string, KernelStat> stats;
+  // scheduler
+  hipStream_t streams[2] = {nullptr, nullptr};
+  std::thread worker, completer;
+  std::mutex qmu;
+  std::condition_variable qcv, fcv;
+  std::deque<std::shared_ptr<Job>> queue;
+  std::deque<InFlight> inflight;
+  std::unordered_map<tfmm_ticket, std::shared_ptr<Job>> jobs;
+  std::atomic<tfmm_ticket> next_ticket{1};
+  bool stop = false;
+  int slot_busy[2] = {0, 0};
+  std::vector<tfmm_op> ops;
+};
+
+// ---------------------------------------------------------------------------
+// Budget and scratch
+// ---------------------------------------------------------------------------
+namespace {
+
+tfmm_status charge(tfmm_ctx c, size_t bytes) {
+  if (c->used + bytes > c->budget)
+    return fail(TFMM_ERR_BUDGET, "device-memory budget exhausted: need " + std::to_string(bytes) + " B, " +
+                                     std::to_string(c->budget - c->used) + " B left");
+  c->used += bytes;
+  return TFMM_OK;
+}
+
+void uncharge(tfmm_ctx c, size_t bytes) { c->used -= std::min(c->used, bytes); }
+
+tfmm_status dev_alloc(tfmm_ctx c, void** p, size_t bytes) {
+  tfmm_status s = charge(c, bytes);
+  if (s != TFMM_OK) return s;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    uncharge(c, bytes);
+    (void)hipGetLastError();
+    return fail(TFMM_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " B failed");
+  }
+  return TFMM_OK;
+}
+
+void dev_free(tfmm_ctx c, void* p, size_t bytes) {
+  if (p) {
+    (void)hipFree(p);
+    uncharge(c, bytes);
+  }
+}
+
+tfmm_status ensure_scratch(tfmm_ctx c, int slot, size_t bytes, void** out) {
+  ScratchSlot& s = c->scratch[slot];
+  if (s.bytes < bytes) {
+    if (s.ptr) {
+      (void)hipDeviceSynchronize();
+      dev_free(c, s.ptr, s.bytes);
+      s.ptr = nullptr;
+      s.bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    tfmm_status st = dev_alloc(c, &s.ptr, want);
+    if (st != TFMM_OK) {
+      st = dev_alloc(c, &s.ptr, bytes);
+      if (st != TFMM_OK) return st;
+      want = bytes;
+    }
+    s.bytes = want;
+  }
+  *out = s.ptr;
+  return TFMM_OK;
+}
+
+tfmm_status roots_table(tfmm_ctx c, int n3, float2** out) {
+  auto it = c->roots.find(n3);
+  if (it != c->roots.end()) {
+    *out = it->second;
+    return TFMM_OK;
+  }
+  std::vector<float2> h(n3);
+  for (int m = 0; m < n3; ++m) {
+    const double a = -2.0 * 3.14159265358979323846264338327950288 * m / n3;
+    h[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  void* d = nullptr;
+  tfmm_status s = dev_alloc(c, &d, n3 * sizeof(float2));
+  if (s != TFMM_OK) return s;
+  HIP_TRY(hipMemcpy(d, h.data(), n3 * sizeof(float2), hipMemcpyHostToDevice));
+  c->roots[n3] = (float2*)d;
+  *out = (float2*)d;
+  return TFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Operator build from host factors
+// ---------------------------------------------------------------------------
+
+tfmm_status validate_grid(const int K[3]) {
+  for (int i = 0; i < 3; ++i)
+    if (K[i] < 1) return fail(TFMM_ERR_INVALID_ARG, "box grid dimensions must be positive");
+  for (int i = 0; i < 3; ++i)
+    if (!supported_len(2 * K[i]))
+      return fail(TFMM_ERR_UNSUPPORTED,
+                  "box grid dimension " + std::to_string(K[i]) + " unsupported (need 4, 8, 12, 16, 24 or 32)");
+  return TFMM_OK;
+}
+
+int pick_cb(int n2, int nq, int max_cb) {
+  // pencil tile 64*cb must be a multiple of n2 and divide nq; prefer 256 pencils
+  for (int cb : {4, 3, 2, 1}) {
+    const int qt = 64 * cb;
+    if (cb <= max_cb && qt % n2 == 0 && nq % qt == 0) return cb;
+  }
+  return 0;
+}
+
+tfmm_status plan_zstage(tfmm_op op) {
+  const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2];
+  op->nq = n1 * n2;
+  // accumulator registers: (n3/8) * cb * 4 per lane; keep them <= 96
+  op->cb = pick_cb(n2, op->nq, n3 >= 64 ? 2 : (n3 >= 48 ? 3 : 4));
+  if (op->cb == 0) return fail(TFMM_ERR_UNSUPPORTED, "no pencil tiling for this grid");
+  switch (op->fmt) {
+    case TFMM_FMT_FULL: op->zfmt = tfmm::ZF_FULL; break;
+    case TFMM_FMT_TT3D: op->zfmt = tfmm::ZF_TT3D; break;
+    case TFMM_FMT_TT4D: op->zfmt = tfmm::ZF_TT4D; break;
+    default: op->zfmt = tfmm::ZF_TUCKER; break;
+  }
+  op->lds = 0;
+  if (op->zfmt == tfmm::ZF_FULL) return TFMM_OK;
+  // largest ranks over directions bound the LDS need
+  int r1 = 1, r2 = 1;
+  for (int p = 0; p < op->ndir; ++p) {
+    r1 = std::max(r1, op->desc[8 * p + 4]);
+    r2 = std::max(r2, op->desc[8 * p + 5]);
+  }
+  const size_t cap = 96 * 1024;
+  int KC = 16;
+  while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, op->cb, KC, r1, r2) > cap) KC /= 2;
+  size_t need = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, op->cb, KC, r1, r2);
+  if (need > 160 * 1024) return fail(TFMM_ERR_UNSUPPORTED, "ranks too large for the LDS-resident restoration");
+  op->KC = KC;
+  op->lds = (int)need;
+  return TFMM_OK;
+}
+
+tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
+  const tfmm::Factors& F = op->host;
+  const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nd = op->ndir;
+  const long long N = (long long)n1 * n2 * n3;
+  op->nq = n1 * n2;
+  if (op->fmt == TFMM_FMT_FULL) {
+    std::vector<float4> h((size_t)nd * N / 2);
+    for (int p = 0; p < nd; ++p)
+      for (int q = 0; q < op->nq; ++q)
+        for (int zp = 0; zp < n3 / 2; ++zp) {
+          const cd a = F.data[(size_t)p * N + (size_t)q * n3 + 2 * zp];
+          const cd b = F.data[(size_t)p * N + (size_t)q * n3 + 2 * zp + 1];
+          h[((size_t)p * (n3 / 2) + zp) * op->nq + q] =
+              make_float4((float)a.real(), (float)a.imag(), (float)b.real(), (float)b.imag());
+        }
+    op->dev_bytes = h.size() * sizeof(float4);
+    tfmm_status s = dev_alloc(c, (void**)&op->d_full, op->dev_bytes);
+    if (s != TFMM_OK) return s;
+    HIP_TRY(hipMemcpy(op->d_full, h.data(), op->dev_bytes, hipMemcpyHostToDevice));
+    op->stored_elems = (size_t)nd * N;
+    return plan_zstage(op);
+  }
+  // compressed: factors as complex64 in the import layout
+  std::vector<float2> h(F.data.size());
+  for (size_t i = 0; i < h.size(); ++i) h[i] = make_float2((float)F.data[i].real(), (float)F.data[i].imag());
+  op->stored_elems = h.size();
+  op->desc.assign((size_t)8 * nd, 0);
+  const std::vector<int32_t>& r = F.ranks;
+  size_t a1 = 0;
+  if (op->fmt == TFMM_FMT_TUCKER3D) {
+    long long off = 0;
+    for (int p = 0; p < nd; ++p) {
+      const int r1 = r[3 * p], r2 = r[3 * p + 1], r3 = r[3 * p + 2];
+      int* d = &op->desc[8 * p];
+      d[0] = (int)off;
+      d[1] = (int)(off + (long long)r1 * r2 * r3);
+      d[2] = (int)(d[1] + (long long)n1 * r1);
+      d[3] = (int)(d[2] + (long long)n2 * r2);
+      d[4] = r1; d[5] = r2; d[6] = r3;
+      off = d[3] + (long long)n3 * r3;
+    }
+  } else if (op->fmt == TFMM_FMT_TT3D) {
+    long long off = 0;
+    for (int p = 0; p < nd; ++p) {
+      const int r1 = r[2 * p], r2 = r[2 * p + 1];
+      int* d = &op->desc[8 * p];
+      d[1] = (int)off;
+      d[0] = (int)(off + (long long)n1 * r1);
+      d[3] = (int)(d[0] + (long long)r1 * n2 * r2);
+      d[4] = r1; d[5] = r2;
+      off = d[3] + (long long)n3 * r2;
+    }
+  } else if (op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D) {
+    const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3];
+    long long oU1 = (op->fmt == TFMM_FMT_TUCKER4D) ? (long long)r1 * r2 * r3 * r4 : 0;
+    long long oU2 = oU1 + (long long)n1 * r1, oU3 = oU2 + (long long)n2 * r2;
+    for (int p = 0; p < nd; ++p) {
+      int* d = &op->desc[8 * p];
+      d[0] = p * r1 * r2 * r3;
+      d[1] = (int)oU1; d[2] = (int)oU2; d[3] = (int)oU3;
+      d[4] = r1; d[5] = r2; d[6] = r3;
+    }
+    a1 = (size_t)nd * r1 * r2 * r3;                                    // per-direction cores
+    if (op->fmt == TFMM_FMT_HTUCKER4D) a1 += (size_t)nd * r3 * (r[4] + r[5]);  // X1, X2
+    (void)r4;
+  } else if (op->fmt == TFMM_FMT_TT4D) {
+    const int r2 = r[1];
+    for (int p = 0; p < nd; ++p) {
+      int* d = &op->desc[8 * p];
+      d[3] = p * n3 * r2;
+      d[5] = r2;
+    }
+    a1 = (size_t)op->nq * r2 + (size_t)nd * n3 * r2;                  // T1 and V
+  }
+  op->a1_bytes = a1 * sizeof(float2);
+  op->dev_bytes = h.size() * sizeof(float2);
+  tfmm_status s = dev_alloc(c, (void**)&op->d_data, op->dev_bytes);
+  if (s != TFMM_OK) return s;
+  HIP_TRY(hipMemcpy(op->d_data, h.data(), op->dev_bytes, hipMemcpyHostToDevice));
+  s = dev_alloc(c, (void**)&op->d_desc, op->desc.size() * sizeof(int));
+  if (s != TFMM_OK) return s;
+  op->dev_bytes += op->desc.size() * sizeof(int);
+  HIP_TRY(hipMemcpy(op->d_desc, op->desc.data(), op->desc.size() * sizeof(int), hipMemcpyHostToDevice));
+  return plan_zstage(op);
+}
+
+void fill_info(tfmm_op op, double setup_s) {
+  tfmm_op_info& I = op->info;
+  I = tfmm_op_info();
+  I.fmt = op->fmt;
+  I.prec = op->prec;
+  for (int i = 0; i < 3; ++i) {
+    I.K[i] = op->K[i];
+    I.n[i] = op->n[i];
+  }
+  I.n_dir = op->ndir;
+  I.L = op->L;
+  I.bytes_full = (size_t)op->ndir * op->n[0] * op->n[1] * op->n[2] * 8;
+  I.bytes_stored = op->stored_elems * 8;
+  I.elems_stored = op->stored_elems;
+  I.rel_err_fro = op->host.rel_err;
+  I.max_dir_rel_err = op->host.max_dir_err;
+  for (int i = 0; i < 8; ++i) I.ranks[i] = 0;
+  const auto& r = op->host.ranks;
+  if (op->fmt == TFMM_FMT_TUCKER3D || op->fmt == TFMM_FMT_TT3D) {
+    const int k = (op->fmt == TFMM_FMT_TUCKER3D) ? 3 : 2;
+    for (int p = 0; p < op->ndir; ++p)
+      for (int i = 0; i < k; ++i) I.ranks[i] = std::max(I.ranks[i], r[(size_t)k * p + i]);
+  } else {
+    for (size_t i = 0; i < r.size() && i < 8; ++i) I.ranks[i] = r[i];
+  }
+  I.setup_seconds = setup_s;
+}
+
+tfmm_status check_problem(const tfmm_problem* P, int* ndir, int* L, int* nth, int* nph) {
+  if (!P) return fail(TFMM_ERR_INVALID_ARG, "problem is NULL");
+  tfmm_status s = validate_grid(P->K);
+  if (s != TFMM_OK) return s;
+  if ((int)P->fmt < 0 || (int)P->fmt > 5) return fail(TFMM_ERR_INVALID_ARG, "unknown format");
+  if ((int)P->prec < 0 || (int)P->prec > 1) return fail(TFMM_ERR_INVALID_ARG, "unknown precision");
+  if (P->prec == TFMM_PREC_BF16X3) return fail(TFMM_ERR_UNSUPPORTED, "bf16x3 restoration is not built yet");
+  int l = P->L;
+  if (l <= 0) {
+    if (!(P->digits > 0) || !(P->k > 0) || !(P->box_size > 0))
+      return fail(TFMM_ERR_INVALID_ARG, "L == 0 needs positive digits, k and box_size");
+    l = tfmm::multipole_order_ceil(P->k, P->box_size, P->digits);
+  }
+  if (l > 200) return fail(TFMM_ERR_INVALID_ARG, "multipole order too large");
+  int a = P->n_theta > 0 ? P->n_theta : l + 1;
+  int b = P->n_phi > 0 ? P->n_phi : 2 * (l + 1);
+  if ((P->n_theta > 0) != (P->n_phi > 0)) return fail(TFMM_ERR_INVALID_ARG, "set both n_theta and n_phi or neither");
+  if (a < 1 || b < 1 || (long long)a * b > 100000) return fail(TFMM_ERR_INVALID_ARG, "bad direction grid");
+  *L = l;
+  *nth = a;
+  *nph = b;
+  *ndir = a * b;
+  return TFMM_OK;
+}
+
+tfmm_op new_op(tfmm_ctx c, const tfmm_problem* P, int ndir, int L) {
+  tfmm_op op = new tfmm_op_s();
+  op->ctx = c;
+  op->fmt = P->fmt;
+  op->prec = P->prec;
+  for (int i = 0; i < 3; ++i) {
+    op->K[i] = P->K[i];
+    op->n[i] = 2 * P->K[i];
+  }
+  op->ndir = ndir;
+  op->L = L;
+  return op;
+}
+
+void free_op(tfmm_ctx c, tfmm_op op) {
+  if (op->d_full) dev_free(c, op->d_full, (size_t)op->ndir * op->n[0] * op->n[1] * op->n[2] * 8);
+  if (op->d_data) dev_free(c, op->d_data, op->stored_elems * sizeof(float2));
+  if (op->d_desc) dev_free(c, op->d_desc, op->desc.size() * sizeof(int));
+  delete op;
+}
+
+// ---------------------------------------------------------------------------
+// Translation orchestration
+// ---------------------------------------------------------------------------
+
+struct Launch {
+  tfmm_ctx c;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  const char* name;
+  Launch(tfmm_ctx c_, hipStream_t s, const char* n) : c(c_), st(s), name(n) {
+    if (c->prof) {
+      (void)hipEventCreate(&a);
+      (void)hipEventRecord(a, st);
+    }
+  }
+  void done() {
+    if (c->prof) {
+      hipEvent_t b;
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(b, st);
+      c->pending.push_back({name, a, b});
+    }
+  }
+};
+
+tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
+  using tfmm::GOp;
+  const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nd = op->ndir;
+  const auto& r = op->host.ranks;
+  const float2* D = op->d_data;
+  if (op->fmt == TFMM_FMT_TUCKER4D) {
+    const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3];
+    const int m = r1 * r2 * r3;
+    const long long oU4 = (long long)m * r4 + (long long)n1 * r1 + (long long)n2 * r2 + (long long)n3 * r3;
+    Launch L(c, st, "a1_tucker4d");
+    HIP_TRY(tfmm::launch_cgemm(m, nd, r4, 1, GOp{D, r4, 1, 0}, GOp{D + oU4, 1, r4, 0}, scr, 1, m, 0, st));
+    L.done();
+  } else if (op->fmt == TFMM_FMT_HTUCKER4D) {
+    const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3], r12 = r[4], r34 = r[5];
+    const long long oU4 = (long long)n1 * r1 + (long long)n2 * r2 + (long long)n3 * r3;
+    const long long oC12 = oU4 + (long long)nd * r4, oC34 = oC12 + (long long)r1 * r2 * r12,
+                    oB = oC34 + (long long)r3 * r4 * r34;
+    float2* Cp = scr;
+    float2* X1 = Cp + (size_t)nd * r1 * r2 * r3;
+    float2* X2 = X1 + (size_t)nd * r3 * r34;
+    Launch L(c, st, "a1_htucker4d");
+    // X1[p][a3][b'] = sum_a4 C34[a3][a4][b'] U4[p][a4]     (Fig. 3(c): C1 times row p of U4)
+    HIP_TRY(tfmm::launch_cgemm(r34, nd, r4, r3, GOp{D + oC34, 1, r34, (long long)r4 * r34}, GOp{D + oU4, 1, r4, 0},
+                               X1, 1, (long long)r3 * r34, r34, st));
+    // X2[p][a3][b] = sum_b' X1[p][a3][b'] B[b][b']            (times the transfer matrix)
+    HIP_TRY(tfmm::launch_cgemm(nd * r3, r12, r34, 1, GOp{X1, r34, 1, 0}, GOp{D + oB, 1, r34, 0}, X2, r12, 1, 0, st));
+    // Cp[p][a1 a2][a3] = sum_b C12[a1 a2][b] X2[p][a3][b]     (times C2)
+    HIP_TRY(tfmm::launch_cgemm(r1 * r2, r3, r12, nd, GOp{D + oC12, r12, 1, 0}, GOp{X2, 1, r12, (long long)r3 * r12},
+                               Cp, r3, 1, (long long)r1 * r2 * r3, st));
+    L.done();
+  } else if (op->fmt == TFMM_FMT_TT4D) {
+    const int r1 = r[0], r2 = r[1], r3 = r[2];
+    const long long oC1 = (long long)n1 * r1, oC2 = oC1 + (long long)r1 * n2 * r2,
+                    oU3 = oC2 + (long long)r2 * n3 * r3;
+    float2* T1 = scr;
+    float2* V = T1 + (size_t)op->nq * r2;
+    Launch L(c, st, "a1_tt4d");
+    // T1[(x,y)][b] = sum_a U1[x][a] C1[a][y][b]               (Fig. 4(a) step 1, shared by all p)
+    HIP_TRY(tfmm::launch_cgemm(n1, r2, r1, n2, GOp{D, r1, 1, 0}, GOp{D + oC1, (long long)n2 * r2, 1, r2}, T1,
+                               (long long)n2 * r2, 1, r2, st));
+    // V[p][z][b] = sum_c C2[b][z][c] U3[p][c]                  (Fig. 4(b) step 1, column p)
+    HIP_TRY(tfmm::launch_cgemm(n3, nd, r3, r2, GOp{D + oC2, r3, 1, (long long)n3 * r3}, GOp{D + oU3, 1, r3, 0}, V,
+                               r2, (long long)n3 * r2, 1, st));
+    L.done();
+  }
+  return TFMM_OK;
+}
+
+// Translate `nr` right-hand sides given by pointer tables, using scratch slot `slot`.
+tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2*>& As,
+                          const std::vector<float2*>& Bs, hipStream_t st, int slot) {
+  const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], K3 = op->K[2], nd = op->ndir;
+  const size_t per_dir_rhs = (size_t)K3 * op->nq * sizeof(float2);
+  const int nr_total = (int)As.size();
+  const size_t hcap = (size_t)256 << 20;  // half-spectrum scratch per chunk
+  const int rhs_group = std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH);
+  int ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, hcap / (per_dir_rhs * rhs_group)));
+  const size_t hbytes = per_dir_rhs * rhs_group * ndl;
+  void* scr = nullptr;
+  tfmm_status s = ensure_scratch(c, slot, hbytes + op->a1_bytes, &scr);
+  if (s != TFMM_OK) return s;
+  float2* H = (float2*)scr;
+  float2* a1 = (float2*)((char*)scr + hbytes);
+  if (op->a1_bytes) {
+    s = run_a1(c, op, a1, st);
+    if (s != TFMM_OK) return s;
+  }
+  float2* roots = nullptr;
+  s = roots_table(c, n3, &roots);
+  if (s != TFMM_OK) return s;
+  tfmm::ZArgs z{};
+  z.fmt = op->zfmt;
+  z.n1 = n1; z.n2 = n2; z.n3 = n3; z.K3 = K3; z.nq = op->nq;
+  z.H = H;
+  z.Tfull = op->d_full;
+  z.fbase = op->d_data;
+  const bool four_d = op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D;
+  z.cbase = four_d ? a1 : op->d_data;
+  z.wbase = a1;
+  z.vbase = a1 + (op->fmt == TFMM_FMT_TT4D ? (size_t)op->nq * op->host.ranks[1] : 0);
+  z.desc = op->d_desc;
+  z.roots = roots;
+  z.KC = op->KC;
+  z.cb = op->cb;
+  z.lds_bytes = op->lds;
+  const float scale = 1.0f / (float)((double)n1 * n2 * n3);
+  for (int r0 = 0; r0 < nr_total; r0 += rhs_group) {
+    const int nr = std::min(rhs_group, nr_total - r0);
+    tfmm::RhsPtrs P{};
+    for (int i = 0; i < nr; ++i) {
+      P.a[i] = As[r0 + i];
+      P.b[i] = Bs[r0 + i];
+    }
+    for (int p0 = 0; p0 < nd; p0 += ndl) {
+      const int nl = std::min(ndl, nd - p0);
+      bool ok = false;
+      {
+        Launch L(c, st, "fwd_xy");
+        HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, st, &ok));
+        L.done();
+      }
+      if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "xy-FFT sizes unsupported");
+      z.p0 = p0;
+      z.nrhs = nr;
+      z.ndl = nl;
+      {
+        Launch L(c, st, op->zfmt == tfmm::ZF_FULL ? "zstage_full" : "zstage_restore");
+        HIP_TRY(tfmm::launch_zstage(z, st, &ok));
+        L.done();
+      }
+      if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "z-stage size unsupported");
+      {
+        Launch L(c, st, "inv_xy");
+        HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, scale, st, &ok));
+        L.done();
+      }
+    }
+  }
+  return TFMM_OK;
+}
+
+tfmm_status translate_contiguous(tfmm_ctx c, tfmm_op op, const void* A, void* B, int nrhs, hipStream_t st,
+                                 int slot) {
+  const size_t blk = (size_t)op->ndir * op->K[0] * op->K[1] * op->K[2];
+  std::vector<const float2*> As(nrhs);
+  std::vector<float2*> Bs(nrhs);
+  for (int s = 0; s < nrhs; ++s) {
+    As[s] = (const float2*)A + s * blk;
+    Bs[s] = (float2*)B + s * blk;
+  }
+  return run_translate(c, op, As, Bs, st, slot);
+}
+
+// ---------------------------------------------------------------------------
+// Scheduler: a worker thread admits queued jobs, coalesces the ones on the same
+// operator into one batched launch per stream slot, and a completer thread
+// stamps completion when the slot's event fires.
+// ---------------------------------------------------------------------------
+
+void worker_loop(tfmm_ctx c) {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    std::vector<std::shared_ptr<Job>> batch;
+    int slot = -1;
+    {
+      std::unique_lock<std::mutex> lk(c->qmu);
+      c->qcv.wait(lk, [&] {
+        return c->stop || (!c->queue.empty() && (c->slot_busy[0] == 0 || c->slot_busy[1] == 0));
+      });
+      if (c->stop && c->queue.empty()) return;
+      slot = c->slot_busy[0] == 0 ? 0 : 1;
+      // coalesce every queued job on the operator of the oldest job (up to 4 x the launch RHS cap)
+      tfmm_op op = c->queue.front()->op;
+      int nr = 0;
+      for (auto it = c->queue.begin(); it != c->queue.end();) {
+        if ((*it)->op == op && nr + (*it)->nrhs <= 4 * TFMM_MAX_RHS_PER_LAUNCH) {
+          nr += (*it)->nrhs;
+          batch.push_back(*it);
+          it = c->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      c->slot_busy[slot] = 1;
+    }
+    tfmm_op op = batch.front()->op;
+    std::vector<const float2*> As;
+    std::vector<float2*> Bs;
+    const size_t blk = (size_t)op->ndir * op->K[0] * op->K[1] * op->K[2];
+    for (auto& j : batch)
+      for (int s = 0; s < j->nrhs; ++s) {
+        As.push_back(j->A + s * blk);
+        Bs.push_back(j->B + s * blk);
+      }
+    tfmm_status st;
+    hipEvent_t ev = nullptr;
+    {
+      std::lock_guard<std::recursive_mutex> g(c->mu);
+      st = run_translate(c, op, As, Bs, c->streams[slot], 1 + slot);
+      if (st == TFMM_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess)
+        (void)hipEventRecord(ev, c->streams[slot]);
+    }
+    InFlight f;
+    f.ev = ev;
+    f.jobs = batch;
+    f.slot = slot;
+    if (st != TFMM_OK || !ev) {
+      for (auto& j : batch) j->status = st != TFMM_OK ? st : TFMM_ERR_HIP;
+      f.ev = nullptr;
+    }
+    {
+      std::lock_guard<std::mutex> lk(c->qmu);
+      c->inflight.push_back(std::move(f));
+    }
+    c->fcv.notify_all();
+  }
+}
+
+void completer_loop(tfmm_ctx c) {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    InFlight f;
+    {
+      std::unique_lock<std::mutex> lk(c->qmu);
+      c->fcv.wait(lk, [&] { return c->stop || !c->inflight.empty(); });
+      if (c->inflight.empty()) return;
+      f = std::move(c->inflight.front());
+      c->inflight.pop_front();
+    }
+    tfmm_status st = TFMM_OK;
+    if (f.ev) {
+      if (hipEventSynchronize(f.ev) != hipSuccess) st = TFMM_ERR_HIP;
+      (void)hipEventDestroy(f.ev);
+    }
+    const double t = now_s();
+    {
+      std::lock_guard<std::mutex> lk(c->qmu);
+      for (auto& j : f.jobs) {
+        if (j->status == TFMM_OK) j->status = st;
+        j->t_done = t;
+        j->op->refs.fetch_sub(1);
+        j->done.store(1);
+      }
+      c->slot_busy[f.slot] = 0;
+    }
+    c->qcv.notify_all();
+    c->fcv.notify_all();
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* tfmm_status_str(tfmm_status s) {
+  switch (s) {
+    case TFMM_OK: return "ok";
+    case TFMM_ERR_INVALID_ARG: return "invalid argument";
+    case TFMM_ERR_UNSUPPORTED: return "unsupported";
+    case TFMM_ERR_BUDGET: return "device-memory budget exhausted";
+    case TFMM_ERR_OOM: return "out of memory";
+    case TFMM_ERR_HIP: return "HIP error";
+    case TFMM_ERR_BUSY: return "operator busy";
+    case TFMM_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    case TFMM_ERR_QUEUE_FULL: return "queue full";
+    case TFMM_ERR_INTERNAL: return "internal error";
+    case TFMM_ERR_NO_DEVICE: return "no HIP device";
+  }
+  return "unknown status";
+}
+
+const char* tfmm_last_error(void) { return g_last_error.c_str(); }
+
+tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
+  if (!out) return fail(TFMM_ERR_INVALID_ARG, "out is NULL");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    return fail(TFMM_ERR_NO_DEVICE, "no HIP device visible");
+  }
+  if (device < 0 || device >= count) return fail(TFMM_ERR_INVALID_ARG, "device index out of range");
+  HIP_TRY(hipSetDevice(device));
+  size_t freeb = 0, total = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &total));
+  tfmm_ctx c = new tfmm_ctx_s();
+  c->device = device;
+  c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+  for (int i = 0; i < 2; ++i)
+    if (hipStreamCreateWithFlags(&c->streams[i], hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(TFMM_ERR_HIP, "stream creation failed");
+    }
+  c->worker = std::thread(worker_loop, c);
+  c->completer = std::thread(completer_loop, c);
+  *out = c;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_ctx_destroy(tfmm_ctx c) {
+  if (!c) return fail(TFMM_ERR_INVALID_ARG, "ctx is NULL");
+  {
+    std::unique_lock<std::mutex> lk(c->qmu);
+    c->fcv.wait(lk, [&] { return c->queue.empty() && c->inflight.empty() && !c->slot_busy[0] && !c->slot_busy[1]; });
+    c->stop = true;
+  }
+  c->qcv.notify_all();
+  c->worker.join();
+  c->fcv.notify_all();
+  c->completer.join();
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  for (auto& p : c->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (tfmm_op op : c->ops) free_op(c, op);
+  for (auto& kv : c->roots) (void)hipFree(kv.second);
+  for (auto& s : c->scratch)
+    if (s.ptr) (void)hipFree(s.ptr);
+  for (auto& s : c->streams) (void)hipStreamDestroy(s);
+  delete c;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_ctx_memory(tfmm_ctx c, size_t* used, size_t* budget) {
+  if (!c) return fail(TFMM_ERR_INVALID_ARG, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (used) *used = c->used;
+  if (budget) *budget = c->budget;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* out) {
+  if (!c || !out) return fail(TFMM_ERR_INVALID_ARG, "ctx or out is NULL");
+  int ndir, L, nth, nph;
+  tfmm_status s = check_problem(P, &ndir, &L, &nth, &nph);
+  if (s != TFMM_OK) return s;
+  if (!(P->k > 0) || !(P->box_size > 0)) return fail(TFMM_ERR_INVALID_ARG, "k and box_size must be positive");
+  if (P->fmt != TFMM_FMT_FULL && !(P->tol >= 0 && P->tol < 1)) return fail(TFMM_ERR_INVALID_ARG, "tol must be in [0, 1)");
+  const double t0 = now_s();
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  std::vector<double> khat, w;
+  tfmm::direction_grid(nth, nph, khat, w);
+  const int n[3] = {2 * P->K[0], 2 * P->K[1], 2 * P->K[2]};
+  const long long N = (long long)n[0] * n[1] * n[2];
+  const size_t tbytes = (size_t)N * ndir * sizeof(double2);
+  // FP64 sampling on the device (temporary buffers, not kept)
+  double* d_khat = nullptr;
+  double2* d_T = nullptr;
+  HIP_TRY(hipMalloc(&d_khat, khat.size() * sizeof(double)));
+  if (hipMalloc(&d_T, tbytes) != hipSuccess) {
+    (void)hipFree(d_khat);
+    (void)hipGetLastError();
+    return fail(TFMM_ERR_OOM, "no device memory for operator sampling");
+  }
+  std::vector<cd> T((size_t)N * ndir);
+  hipError_t e = hipMemcpy(d_khat, khat.data(), khat.size() * sizeof(double), hipMemcpyHostToDevice);
+  const int near_rule = (int)P->near_rule;
+  const double near_param = P->near_param > 0 ? P->near_param : (near_rule == 0 ? 1.0 : 4.0);
+  const bool scale0 = P->scale_re == 0 && P->scale_im == 0;
+  if (e == hipSuccess)
+    e = tfmm::launch_sample(d_T, d_khat, ndir, P->K, P->box_size, P->k, L, near_rule, near_param,
+                            scale0 ? 1.0 : P->scale_re, scale0 ? 0.0 : P->scale_im, 0);
+  if (e == hipSuccess) e = hipMemcpy(T.data(), d_T, tbytes, hipMemcpyDeviceToHost);
+  (void)hipFree(d_T);
+  (void)hipFree(d_khat);
+  if (e != hipSuccess) return fail(TFMM_ERR_HIP, std::string("operator sampling: ") + hipGetErrorString(e));
+  // FP64 FFT and compression on the host
+  tfmm::fft3d_forward(T.data(), n[0], n[1], n[2], ndir);
+  tfmm_op op = new_op(c, P, ndir, L);
+  const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::string err = tfmm::compress_operator(T, ndir, n, (int)P->fmt, P->fmt == TFMM_FMT_FULL ? 0.0 : P->tol, op->host,
+                                            nthreads);
+  if (!err.empty()) {
+    delete op;
+    return fail(TFMM_ERR_INTERNAL, "compression: " + err);
+  }
+  T.clear();
+  T.shrink_to_fit();
+  s = build_device_op(c, op);
+  if (s != TFMM_OK) {
+    free_op(c, op);
+    return s;
+  }
+  fill_info(op, now_s() - t0);
+  c->ops.push_back(op);
+  *out = op;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_op_import(tfmm_ctx c, const tfmm_problem* P, const int32_t* ranks, size_t nranks,
+                           const double* data, size_t ndata, tfmm_op* out) {
+  if (!c || !out) return fail(TFMM_ERR_INVALID_ARG, "ctx or out is NULL");
+  int ndir, L, nth, nph;
+  tfmm_problem Q = *P;
+  if (Q.L <= 0 && Q.n_theta <= 0) return fail(TFMM_ERR_INVALID_ARG, "import needs L or an explicit direction grid");
+  tfmm_status s = check_problem(&Q, &ndir, &L, &nth, &nph);
+  if (s != TFMM_OK) return s;
+  if (nranks && !ranks) return fail(TFMM_ERR_INVALID_ARG, "ranks is NULL");
+  if (!data) return fail(TFMM_ERR_INVALID_ARG, "data is NULL");
+  const int n[3] = {2 * P->K[0], 2 * P->K[1], 2 * P->K[2]};
+  std::vector<int32_t> r(ranks, ranks + nranks);
+  const long long need = tfmm::factor_elems((int)P->fmt, n, ndir, r);
+  if (need < 0) return fail(TFMM_ERR_INVALID_ARG, "ranks inconsistent with the format");
+  if ((long long)ndata != 2 * need)
+    return fail(TFMM_ERR_INVALID_ARG, "data holds " + std::to_string(ndata) + " doubles, format needs " +
+                                          std::to_string(2 * need));
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  tfmm_op op = new_op(c, P, ndir, L);
+  op->host.fmt = (int)P->fmt;
+  for (int i = 0; i < 3; ++i) op->host.n[i] = n[i];
+  op->host.ndir = ndir;
+  op->host.ranks = r;
+  op->host.data.resize((size_t)need);
+  std::memcpy((void*)op->host.data.data(), data, ndata * sizeof(double));
+  op->host.rel_err = -1.0;
+  op->host.max_dir_err = -1.0;
+  s = build_device_op(c, op);
+  if (s != TFMM_OK) {
+    free_op(c, op);
+    return s;
+  }
+  fill_info(op, 0.0);
+  c->ops.push_back(op);
+  *out = op;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_op_info_get(tfmm_op op, tfmm_op_info* out) {
+  if (!op || !out) return fail(TFMM_ERR_INVALID_ARG, "op or out is NULL");
+  *out = op->info;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_op_ranks(tfmm_op op, int32_t* ranks, size_t cap, size_t* need) {
+  if (!op) return fail(TFMM_ERR_INVALID_ARG, "op is NULL");
+  const auto& r = op->host.ranks;
+  if (need) *need = r.size();
+  if (ranks) {
+    if (cap < r.size()) return fail(TFMM_ERR_INVALID_ARG, "ranks buffer too small");
+    std::copy(r.begin(), r.end(), ranks);
+  }
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_op_export(tfmm_op op, double* buf, size_t cap, size_t* need) {
+  if (!op) return fail(TFMM_ERR_INVALID_ARG, "op is NULL");
+  const size_t n = op->host.data.size() * 2;
+  if (need) *need = n;
+  if (buf) {
+    if (cap < n) return fail(TFMM_ERR_INVALID_ARG, "export buffer too small");
+    std::memcpy(buf, (const void*)op->host.data.data(), n * sizeof(double));
+  }
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_op_release(tfmm_ctx c, tfmm_op op) {
+  if (!c || !op) return fail(TFMM_ERR_INVALID_ARG, "ctx or op is NULL");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  auto it = std::find(c->ops.begin(), c->ops.end(), op);
+  if (it == c->ops.end()) return fail(TFMM_ERR_INVALID_ARG, "operator does not belong to this context");
+  if (op->refs.load() > 0) return fail(TFMM_ERR_BUSY, "operator has queued jobs");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->ops.erase(it);
+  free_op(c, op);
+  return TFMM_OK;
+}
+
+static tfmm_status check_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs) {
+  if (!c || !op) return fail(TFMM_ERR_INVALID_ARG, "ctx or op is NULL");
+  if (op->ctx != c) return fail(TFMM_ERR_INVALID_ARG, "operator belongs to another context");
+  if (!A || !B) return fail(TFMM_ERR_INVALID_ARG, "A or B is NULL");
+  if (nrhs < 1) return fail(TFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
+  const size_t bytes = (size_t)nrhs * op->ndir * op->K[0] * op->K[1] * op->K[2] * 8;
+  const char* a = (const char*)A;
+  const char* b = (const char*)B;
+  if (a < b + bytes && b < a + bytes) return fail(TFMM_ERR_INVALID_ARG, "A and B overlap");
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs, void* stream) {
+  tfmm_status s = check_translate(c, op, A, B, nrhs);
+  if (s != TFMM_OK) return s;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  return translate_contiguous(c, op, A, B, nrhs, (hipStream_t)stream, 0);
+}
+
+tfmm_status tfmm_submit(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs, tfmm_ticket* out) {
+  tfmm_status s = check_translate(c, op, A, B, nrhs);
+  if (s != TFMM_OK) return s;
+  if (!out) return fail(TFMM_ERR_INVALID_ARG, "out is NULL");
+  auto j = std::make_shared<Job>();
+  j->id = c->next_ticket.fetch_add(1);
+  j->op = op;
+  j->A = (const float2*)A;
+  j->B = (float2*)B;
+  j->nrhs = nrhs;
+  j->t_submit = now_s();
+  op->refs.fetch_add(1);
+  {
+    std::lock_guard<std::mutex> lk(c->qmu);
+    if (c->queue.size() >= 65536) {
+      op->refs.fetch_sub(1);
+      return fail(TFMM_ERR_QUEUE_FULL, "scheduler queue full");
+    }
+    c->jobs[j->id] = j;
+    c->queue.push_back(j);
+  }
+  c->qcv.notify_all();
+  *out = j->id;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_poll(tfmm_ctx c, tfmm_ticket t, int32_t* done, tfmm_status* job_status, double* latency_us) {
+  if (!c || !done) return fail(TFMM_ERR_INVALID_ARG, "ctx or done is NULL");
+  std::lock_guard<std::mutex> lk(c->qmu);
+  auto it = c->jobs.find(t);
+  if (it == c->jobs.end()) return fail(TFMM_ERR_UNKNOWN_TICKET, "unknown ticket");
+  const auto& j = it->second;
+  *done = j->done.load();
+  if (*done) {
+    if (job_status) *job_status = j->status;
+    if (latency_us) *latency_us = (j->t_done - j->t_submit) * 1e6;
+    c->jobs.erase(it);
+  }
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_wait(tfmm_ctx c, tfmm_ticket t, tfmm_status* job_status, double* latency_us) {
+  if (!c) return fail(TFMM_ERR_INVALID_ARG, "ctx is NULL");
+  std::shared_ptr<Job> j;
+  {
+    std::lock_guard<std::mutex> lk(c->qmu);
+    auto it = c->jobs.find(t);
+    if (it == c->jobs.end()) return fail(TFMM_ERR_UNKNOWN_TICKET, "unknown ticket");
+    j = it->second;
+  }
+  {
+    std::unique_lock<std::mutex> lk(c->qmu);
+    c->fcv.wait(lk, [&] { return j->done.load() != 0; });
+    c->jobs.erase(t);
+  }
+  if (job_status) *job_status = j->status;
+  if (latency_us) *latency_us = (j->t_done - j->t_submit) * 1e6;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_set_profiling(tfmm_ctx c, int32_t on) {
+  if (!c) return fail(TFMM_ERR_INVALID_ARG, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  c->prof = on != 0;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_kernel_times(tfmm_ctx c, char* names, size_t names_cap, double* avg_ms, int32_t* launches,
+                              int32_t cap, int32_t* count) {
+  if (!c) return fail(TFMM_ERR_INVALID_ARG, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  for (auto& p : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->stats[p.name].total_ms += ms;
+      c->stats[p.name].n += 1;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  c->pending.clear();
+  int i = 0;
+  std::string joined;
+  for (auto& kv : c->stats) {
+    if (i < cap) {
+      if (avg_ms) avg_ms[i] = kv.second.n ? kv.second.total_ms / kv.second.n : 0.0;
+      if (launches) launches[i] = kv.second.n;
+    }
+    joined += kv.first;
+    joined += '\n';
+    ++i;
+  }
+  if (count) *count = i;
+  if (names && names_cap) {
+    size_t n = std::min(names_cap - 1, joined.size());
+    std::memcpy(names, joined.data(), n);
+    names[n] = 0;
+  }
+  // a reset happens when the caller passes cap < 0
+  if (cap < 0) c->stats.clear();
+  return TFMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Host-side launch interface of the translation kernels (implemented in kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfmm {
+
+// Operator family seen by the z-stage kernel.
+enum ZFmt { ZF_FULL = 0, ZF_TUCKER = 1, ZF_TT3D = 2, ZF_TT4D = 3 };
+
+// Per-direction restoration descriptor (8 ints, float2 offsets):
+//   Tucker : offC, offU1, offU2, offU3, r1, r2, r3, 0     (C may live in scratch)
+//   TT-3D  : offC, offU1, 0, offU3, r1, r2, 0, 0
+//   TT-4D  : 0, 0, 0, offV, 0, r2, 0, 0                    (V_p in scratch)
+struct ZArgs {
+  int fmt;
+  int n1, n2, n3, K3, nq;
+  int p0, nrhs, ndl;          // first direction, RHS count, directions in this launch
+  float2* H;                  // [nrhs][ndl][K3][nq]
+  const float4* Tfull;        // FULL: [n_dir][n3/2][nq] (consecutive fz pairs)
+  const float2* cbase;        // cores (op data or scratch)
+  const float2* fbase;        // factors (op data)
+  const float2* wbase;        // TT-4D: T1 [nq][r2] (scratch)
+  const float2* vbase;        // TT-4D: V [n_dir][n3][r2] (scratch)
+  const int* desc;            // [n_dir][8]
+  const float2* roots;        // exp(-2 pi i m / n3), m < n3 (FP64-built, rounded)
+  int KC;                     // complex contraction chunk
+  int cb;                     // column blocks per wave (pencil tile = 64*cb)
+  int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
+};
+
+// LDS bytes the z-stage needs for a format / ranks / chunk (host-side planning).
+size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int cb, int KC, int r1, int r2);
+
+// Per-RHS base pointers of one launch: rhs s reads A_s[n_dir][Kx][Ky][Kz] and
+// writes B_s of the same shape (complex64).  Passed by value.
+#define TFMM_MAX_RHS_PER_LAUNCH 32
+struct RhsPtrs {
+  const float2* a[TFMM_MAX_RHS_PER_LAUNCH];
+  float2* b[TFMM_MAX_RHS_PER_LAUNCH];
+};
+
+hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
+                         hipStream_t st, bool* supported);
+hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
+                         float scale, hipStream_t st, bool* supported);
+hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported);
+
+// Batched complex GEMM on global memory: C_b[m][n] = sum_k A_b[m][k] B_b[k][n],
+// element (i, j, b) of X at X.p + i*s0 + j*s1 + b*sb (float2 units).
+struct GOp {
+  const float2* p;
+  long long s0, s1, sb;
+};
+hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
+                        long long csb, hipStream_t st);
+
+// FP64 operator sampling, Eq. (7): T[p][m1][m2][m3] (double2) for every direction.
+hipError_t launch_sample(double2* T, const double* khat, int ndir, const int K[3], double box, double k, int L,
+                         int near_rule, double near_param, double scale_re, double scale_im, hipStream_t st);
+
+// Pack complex64 FULL operator [p][n1 n2 n3] into the [p][n3/2][nq] float4 layout.
+hipError_t launch_pack_full(const float2* src, float4* dst, int ndir, int nq, int n3, hipStream_t st);
+
+}  // namespace tfmm

@@ -1,0 +1,275 @@
+"""ctypes binding of libtfmm (include/tfmm.h): argument marshalling only.
+
+Every computation runs inside libtfmm's HIP kernels.  torch supplies device
+buffers (complex64 tensors) and streams.  There is no CPU fallback: if the
+library is missing or no GPU is visible, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtfmm.so")
+
+FORMATS = {"full": 0, "tucker3d": 1, "tt3d": 2, "tucker4d": 3, "tt4d": 4, "htucker4d": 5}
+FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+PRECISIONS = {"fp32": 0, "bf16x3": 1}
+NEAR = {"cheb": 0, "kappa": 1}
+
+STATUS = {
+    0: "ok", 1: "invalid argument", 2: "unsupported", 3: "device-memory budget exhausted",
+    4: "out of memory", 5: "HIP error", 6: "operator busy", 7: "unknown ticket", 8: "queue full",
+    9: "internal error", 10: "no HIP device",
+}
+
+
+class TfmmError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+        self.detail = detail
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32 * 3),
+        ("box_size", ctypes.c_double),
+        ("k", ctypes.c_double),
+        ("L", ctypes.c_int32),
+        ("digits", ctypes.c_double),
+        ("n_theta", ctypes.c_int32),
+        ("n_phi", ctypes.c_int32),
+        ("near_rule", ctypes.c_int),
+        ("near_param", ctypes.c_double),
+        ("scale_re", ctypes.c_double),
+        ("scale_im", ctypes.c_double),
+        ("fmt", ctypes.c_int),
+        ("tol", ctypes.c_double),
+        ("prec", ctypes.c_int),
+    ]
+
+
+class OpInfo(ctypes.Structure):
+    _fields_ = [
+        ("fmt", ctypes.c_int),
+        ("prec", ctypes.c_int),
+        ("K", ctypes.c_int32 * 3),
+        ("n", ctypes.c_int32 * 3),
+        ("n_dir", ctypes.c_int32),
+        ("L", ctypes.c_int32),
+        ("bytes_full", ctypes.c_size_t),
+        ("bytes_stored", ctypes.c_size_t),
+        ("elems_stored", ctypes.c_size_t),
+        ("rel_err_fro", ctypes.c_double),
+        ("max_dir_rel_err", ctypes.c_double),
+        ("ranks", ctypes.c_int32 * 8),
+        ("setup_seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {
+            "fmt": FORMAT_NAMES.get(self.fmt, self.fmt), "prec": self.prec, "K": tuple(self.K), "n": tuple(self.n),
+            "n_dir": self.n_dir, "L": self.L, "bytes_full": self.bytes_full, "bytes_stored": self.bytes_stored,
+            "elems_stored": self.elems_stored, "rel_err_fro": self.rel_err_fro,
+            "max_dir_rel_err": self.max_dir_rel_err, "ranks": tuple(self.ranks),
+            "setup_seconds": self.setup_seconds,
+        }
+
+
+_VP = ctypes.c_void_p
+_ST = ctypes.c_int
+
+# (name, restype, argtypes) for every entry point declared in include/tfmm.h
+SIGNATURES = [
+    ("tfmm_ctx_create", _ST, [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    ("tfmm_ctx_destroy", _ST, [_VP]),
+    ("tfmm_ctx_memory", _ST, [_VP, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    ("tfmm_setup_compressed", _ST, [_VP, ctypes.POINTER(Problem), ctypes.POINTER(_VP)]),
+    ("tfmm_op_import", _ST, [_VP, ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t,
+                             ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, ctypes.POINTER(_VP)]),
+    ("tfmm_op_info_get", _ST, [_VP, ctypes.POINTER(OpInfo)]),
+    ("tfmm_op_ranks", _ST, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    ("tfmm_op_export", _ST, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    ("tfmm_op_release", _ST, [_VP, _VP]),
+    ("tfmm_translate", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    ("tfmm_submit", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
+    ("tfmm_poll", _ST, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_double)]),
+    ("tfmm_wait", _ST, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]),
+    ("tfmm_status_str", ctypes.c_char_p, [ctypes.c_int]),
+    ("tfmm_last_error", ctypes.c_char_p, []),
+    ("tfmm_set_profiling", _ST, [_VP, ctypes.c_int32]),
+    ("tfmm_kernel_times", _ST, [_VP, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libtfmm and declare its signatures.  Raises if the library was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtfmm not built ({path} missing); run paper_2010_00520_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise TfmmError(status, load().tfmm_last_error().decode())
+
+
+def make_problem(K, box=0.5, k=2 * np.pi, L=0, digits=0.0, fmt="full", tol=1e-4, prec="fp32", near="cheb",
+                 near_param=0.0, n_theta=0, n_phi=0, scale=1.0 + 0j) -> Problem:
+    p = Problem()
+    p.K[:] = [int(x) for x in K]
+    p.box_size = float(box)
+    p.k = float(k)
+    p.L = int(L)
+    p.digits = float(digits)
+    p.n_theta, p.n_phi = int(n_theta), int(n_phi)
+    p.near_rule = NEAR[near]
+    p.near_param = float(near_param)
+    p.scale_re, p.scale_im = float(np.real(scale)), float(np.imag(scale))
+    p.fmt = FORMATS[fmt]
+    p.tol = float(tol)
+    p.prec = PRECISIONS[prec]
+    return p
+
+
+def _dev_ptr(t) -> int:
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) torch tensor")
+    if t.dtype != torch.complex64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous complex64 tensor")
+    return t.data_ptr()
+
+
+def _stream_handle(stream) -> int:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+class Operator:
+    def __init__(self, ctx: "Context", handle: int):
+        self.ctx = ctx
+        self.handle = ctypes.c_void_p(handle)
+
+    def info(self) -> dict:
+        inf = OpInfo()
+        _check(load().tfmm_op_info_get(self.handle, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    def ranks(self) -> np.ndarray:
+        need = ctypes.c_size_t()
+        _check(load().tfmm_op_ranks(self.handle, None, 0, ctypes.byref(need)))
+        buf = (ctypes.c_int32 * max(1, need.value))()
+        _check(load().tfmm_op_ranks(self.handle, buf, need.value, ctypes.byref(need)))
+        return np.array(buf[: need.value], dtype=np.int32)
+
+    def export(self) -> np.ndarray:
+        need = ctypes.c_size_t()
+        _check(load().tfmm_op_export(self.handle, None, 0, ctypes.byref(need)))
+        arr = np.empty(need.value, dtype=np.float64)
+        _check(load().tfmm_op_export(self.handle, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), need.value,
+                                     ctypes.byref(need)))
+        return arr.view(np.complex128)
+
+    def release(self):
+        if self.handle:
+            _check(load().tfmm_op_release(self.ctx.handle, self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+
+class Context:
+    """One GPU, one device-memory budget, one scheduler."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.tfmm_ctx_create(int(device), int(budget_bytes), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            _check(load().tfmm_ctx_destroy(self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def memory(self) -> Tuple[int, int]:
+        u, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load().tfmm_ctx_memory(self.handle, ctypes.byref(u), ctypes.byref(b)))
+        return u.value, b.value
+
+    def setup(self, **kw) -> Operator:
+        prob = make_problem(**kw)
+        h = ctypes.c_void_p()
+        _check(load().tfmm_setup_compressed(self.handle, ctypes.byref(prob), ctypes.byref(h)))
+        return Operator(self, h.value)
+
+    def import_factors(self, K, L, fmt: str, ranks: Sequence[int], data: np.ndarray, prec="fp32", n_theta=0,
+                       n_phi=0) -> Operator:
+        prob = make_problem(K, L=L, fmt=fmt, prec=prec, n_theta=n_theta, n_phi=n_phi)
+        r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32).ravel())
+        d = np.ascontiguousarray(np.asarray(data, dtype=np.complex128).ravel()).view(np.float64)
+        h = ctypes.c_void_p()
+        _check(load().tfmm_op_import(self.handle, ctypes.byref(prob),
+                                     r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), r.size,
+                                     d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d.size, ctypes.byref(h)))
+        return Operator(self, h.value)
+
+    def translate(self, op: Operator, A, B, stream=None):
+        """Enqueue B = translate(A) on `stream` (torch stream; default: current)."""
+        nrhs = int(A.shape[0])
+        _check(load().tfmm_translate(self.handle, op.handle, ctypes.c_void_p(_dev_ptr(A)),
+                                     ctypes.c_void_p(_dev_ptr(B)), nrhs, ctypes.c_void_p(_stream_handle(stream))))
+
+    def submit(self, op: Operator, A, B) -> int:
+        t = ctypes.c_uint64()
+        _check(load().tfmm_submit(self.handle, op.handle, ctypes.c_void_p(_dev_ptr(A)), ctypes.c_void_p(_dev_ptr(B)),
+                                  int(A.shape[0]), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        done, st, lat = ctypes.c_int32(), ctypes.c_int(), ctypes.c_double()
+        _check(load().tfmm_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(lat)))
+        return bool(done.value), st.value, lat.value
+
+    def wait(self, ticket: int):
+        st, lat = ctypes.c_int(), ctypes.c_double()
+        _check(load().tfmm_wait(self.handle, ticket, ctypes.byref(st), ctypes.byref(lat)))
+        return st.value, lat.value
+
+    def set_profiling(self, on: bool):
+        _check(load().tfmm_set_profiling(self.handle, 1 if on else 0))
+
+    def kernel_times(self, reset: bool = False) -> dict:
+        cap = 64
+        names = ctypes.create_string_buffer(8192)
+        avg = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        _check(load().tfmm_kernel_times(self.handle, names, 8192, avg, cnt, -cap if reset else cap, ctypes.byref(n)))
+        keys = [k for k in names.value.decode().split("\n") if k]
+        return {k: {"avg_ms": avg[i], "launches": cnt[i]} for i, k in enumerate(keys[: min(n.value, cap)])}

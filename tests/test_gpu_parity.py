@@ -1,0 +1,141 @@
+"""GPU parity: libtfmm's HIP translation against the FP64 oracle, through the C ABI.
+
+Two kinds of checks:
+* arithmetic parity -- the same synthetic factors go to the oracle's restoration
+  (Figs. 3-4) + Eq. (5) and to the library via tfmm_op_import; the FP32 GPU
+  result must match to 2e-5 relative L2 (FP32 FFTs of length <= 64 and
+  FP32 contractions of length <= 64 stay near 1e-6);
+* end-to-end parity -- the library samples, FFTs and compresses the operator
+  itself (tfmm_setup_compressed); its result must match the exact FP64
+  translation (the plain pairwise sum, or the FFT form with the exact
+  operator) within 10*gamma + 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from factor_layout import random_factors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+ARITH_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2010_00520_amd as P
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_translate(ctx, op, A):
+    Ad = torch.from_numpy(np.ascontiguousarray(A.astype(np.complex64))).to("cuda")
+    Bd = torch.zeros_like(Ad)
+    ctx.translate(op, Ad, Bd)
+    torch.cuda.synchronize()
+    return Bd.cpu().numpy().astype(np.complex128)
+
+
+def test_full_tiny_matches_direct_sum(ctx):
+    w = synth.TINY
+    op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
+    info = op.info()
+    assert info["n_dir"] == 72 and info["L"] == 5
+    A = synth.patterns_for(w, nrhs=2)
+    khat, _ = O.directions(w.L)
+    T = O.sample_operator(w.K, w.box, w.k, w.L, khat)
+    ref = O.translate_direct(A, T)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, ref) < ARITH_TOL
+    op.release()
+
+
+@pytest.mark.parametrize("K", [(8, 8, 8), (8, 12, 4), (4, 16, 8)])
+@pytest.mark.parametrize("fmt", ["full", "tucker3d", "tt3d", "tucker4d", "tt4d", "htucker4d"])
+def test_import_arithmetic_parity(ctx, fmt, K):
+    n = tuple(2 * k for k in K)
+    L = 3
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(abs(hash((fmt, K))) % (2 ** 32))
+    ranks = {"tucker4d": (5, 6, 3, 7), "tt4d": (5, 9, 7), "htucker4d": (4, 5, 3, 6, 9, 8)}.get(fmt)
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    op = ctx.import_factors(K, L, fmt, rk, data)
+    A = synth.gaussian_patterns((2, ndir) + tuple(K), 7)
+    ref = O.translate_compressed(A, comp)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, ref) < ARITH_TOL, (fmt, K)
+    # per-RHS and per-direction check too (a wrong direction index would hide in the global norm)
+    for s in range(2):
+        for p in (0, ndir // 2, ndir - 1):
+            assert O.rel_l2(got[s, p], ref[s, p]) < 5 * ARITH_TOL
+    op.release()
+
+
+@pytest.mark.parametrize("fmt", ["tucker3d", "tt3d", "tucker4d", "tt4d", "htucker4d"])
+def test_setup_end_to_end_tiny(ctx, fmt):
+    w = synth.TINY
+    gamma = 1e-4
+    op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=gamma)
+    info = op.info()
+    assert info["rel_err_fro"] <= gamma * 1.05
+    A = synth.patterns_for(w, nrhs=1)
+    khat, _ = O.directions(w.L)
+    T = O.sample_operator(w.K, w.box, w.k, w.L, khat)
+    ref = O.translate_direct(A, T)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, ref) <= 10 * gamma + 1e-6
+    op.release()
+
+
+def test_plain_16cubed_tucker3d_end_to_end(ctx):
+    w = synth.PLAIN
+    op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="tucker3d", tol=w.tol)
+    info = op.info()
+    assert info["n_dir"] == 242
+    assert info["rel_err_fro"] <= w.tol * 1.05
+    A = synth.patterns_for(w)
+    _, _, _, Th = O.build_operator(w.K, w.box, w.k, w.L)
+    ref = O.translate_fft(A, Th)
+    got = gpu_translate(ctx, op, A)
+    err = O.rel_l2(got, ref)
+    assert err <= 10 * w.tol + 1e-6
+    # every direction individually within the bound as well
+    per = [O.rel_l2(got[0, p], ref[0, p]) for p in range(0, 242, 11)]
+    assert max(per) <= 10 * w.tol + 1e-6
+    op.release()
+
+
+def test_plain_16cubed_full_matches_exact(ctx):
+    w = synth.PLAIN
+    op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
+    A = synth.patterns_for(w)
+    _, _, _, Th = O.build_operator(w.K, w.box, w.k, w.L)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, O.translate_fft(A, Th)) < ARITH_TOL
+    op.release()
+
+
+def test_invalid_arguments(ctx):
+    import paper_2010_00520_amd as P
+
+    op = ctx.setup(K=(4, 4, 4), box=0.5, L=3, fmt="full")
+    A = torch.zeros((1, 32, 4, 4, 4), dtype=torch.complex64, device="cuda")
+    with pytest.raises(P.TfmmError) as e:
+        ctx.translate(op, A, A)  # aliasing
+    assert e.value.status == 1
+    with pytest.raises(P.TfmmError) as e:
+        ctx.setup(K=(5, 4, 4), box=0.5, L=3, fmt="full")
+    assert e.value.status == 2
+    with pytest.raises(P.TfmmError) as e:
+        ctx.import_factors((4, 4, 4), 3, "tucker4d", [2, 2, 2], np.zeros(10))
+    assert e.value.status == 1
+    op.release()
