@@ -1,0 +1,275 @@
+"""Benchmark: compressed vs uncompressed FFT-based FMM translation on one MI355X.
+
+One step = one tfmm_translate call: for every plane-wave direction and every
+right-hand side, restore the FFT'ed operator from its compressed form, FFT the
+zero-padded patterns, multiply, inverse-FFT and crop (Eq. (5)).  Inputs are
+resident in device memory before the timed region starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload plain|batching|precision]
+
+Prints one JSON line (rank 0).  The metric is translated grid points x
+directions per second (boxes x directions x RHS / step time) of the
+compressed operator; the uncompressed (FULL) operator is timed the same way
+and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_FP32_VALU_TFLOPS = 157.3  # packed; non-packed issue is half of it
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--workload", default="plain", choices=["plain", "batching", "precision", "tiny"])
+    ap.add_argument("--fmt", default=None, help="override the compressed format")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def workload(name):
+    return {"plain": synth.PLAIN, "batching": synth.BATCHING, "precision": synth.PRECISION,
+            "tiny": synth.TINY}[name]
+
+
+def restore_flops(fmt, ranks, n, ndir):
+    """Real flops of the restoration contractions per launch (8 per complex MAC), shared over RHS."""
+    n1, n2, n3 = n
+    N = n1 * n2 * n3
+    cm = 0
+    if fmt == "tucker3d":
+        r = np.asarray(ranks).reshape(-1, 3)
+        for r1, r2, r3 in r:
+            cm += n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3
+    elif fmt == "tt3d":
+        r = np.asarray(ranks).reshape(-1, 2)
+        for r1, r2 in r:
+            cm += n1 * r1 * n2 * r2 + N * r2
+    elif fmt == "tucker4d":
+        r1, r2, r3, r4 = ranks
+        cm += ndir * (r1 * r2 * r3 * r4 + n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3)
+    elif fmt == "htucker4d":
+        r1, r2, r3, r4, r12, r34 = ranks
+        cm += ndir * (r3 * r4 * r34 + r3 * r34 * r12 + r1 * r2 * r12 * r3 + n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3
+                      + N * r3)
+    elif fmt == "tt4d":
+        r1, r2, r3 = ranks
+        cm += n1 * r1 * n2 * r2 + ndir * (r2 * n3 * r3 + N * r2)
+    return 8.0 * cm
+
+
+def fft_flops(K, n, ndir, nrhs):
+    """Real flops of the pruned forward + inverse 3-D FFTs (5 m log2 m per line of length m)."""
+    (K1, K2, K3), (n1, n2, n3) = K, n
+    f = lambda m: 5.0 * m * math.log2(m)
+    lines = (K2 * K3 * f(n1) + n1 * K3 * f(n2) + n1 * n2 * f(n3)) * 2
+    return nrhs * ndir * (lines + 6.0 * n1 * n2 * n3)
+
+
+def time_steps(ctx, op, A, B, steps, warmup, torch):
+    st = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.translate(op, A, B)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    ctx.kernel_times(reset=True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(st)
+        ctx.translate(op, A, B)
+        evs[i][1].record(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.set_profiling(False)
+    kt = ctx.kernel_times(reset=True)
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    return (t1 - t0) / steps * 1e3, lat, kt
+
+
+def cpu_baseline(w, fmt, gpu_B, A_np, target_s):
+    """The FP64 oracle on a bounded sample of directions: restoration + FFT convolution timed
+    on the host; also the reference the GPU result is checked against on that sample."""
+    import oracle as O
+
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    khat, _ = O.directions(w.L, w.grid)
+    ndir = khat.shape[0]
+    rng = np.random.default_rng(12345)
+    # grow the sample until it costs about target_s seconds
+    sample = []
+    t_total = 0.0
+    errs, errs_exact = [], []
+    order = rng.permutation(ndir)
+    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        for p in order:
+            T = O.sample_operator(w.K, w.box, w.k, w.L, khat[p:p + 1])
+            Th = O.fft_operator(T)
+            comp = O.compress(Th, fmt, w.tol) if fmt != "full" else {"fmt": "full", "T": Th}
+            Ap = A_np[:, p:p + 1].astype(np.complex128)
+            t0 = time.perf_counter()
+            Bc = O.translate_compressed(Ap, comp)
+            t_total += time.perf_counter() - t0
+            Bex = O.translate_fft(Ap, Th)
+            errs.append(O.rel_l2(gpu_B[:, p:p + 1], Bex))
+            errs_exact.append(O.rel_l2(Bc, Bex))
+            sample.append(int(p))
+            if t_total >= target_s or len(sample) >= ndir:
+                break
+    finally:
+        if ctxm is not None:
+            ctxm.__exit__(None, None, None)
+    units = w.boxes * len(sample) * A_np.shape[0]
+    return {
+        "value": units / t_total,
+        "unit": "grid-pts*dirs/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{len(sample)} of {ndir} directions x {A_np.shape[0]} RHS of the {w.name} workload "
+                  f"({fmt} restore + FFT convolution, FP64 numpy, 1 thread); {t_total:.1f} s",
+        "cpu": platform.processor() or platform.machine(),
+        "gpu_rel_err_max": float(max(errs)),
+        "gpu_rel_err_median": float(np.median(errs)),
+        "oracle_compressed_rel_err_max": float(max(errs_exact)),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2010_00520_amd as P
+
+    w = workload(args.workload)
+    fmt = args.fmt or w.fmt
+    A_np = synth.patterns_for(w)
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(A_np).to(dev)
+    B = torch.zeros_like(A)
+    Bf = torch.zeros_like(A)
+    out = {}
+    with P.Context(0) as ctx:
+        t0 = time.perf_counter()
+        op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=w.precision)
+        setup_s = time.perf_counter() - t0
+        full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
+        info, finfo = op.info(), full.info()
+        ranks = op.ranks()
+        ms, lat, kt = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
+        ms_f, lat_f, kt_f = time_steps(ctx, full, A, Bf, args.steps, args.warmup, torch)
+        gpu_B = B.cpu().numpy().astype(np.complex128)
+        gpu_Bf = Bf.cpu().numpy().astype(np.complex128)
+        op.release()
+        full.release()
+
+    ndir, nrhs = w.n_dir, w.nrhs
+    units = w.boxes * ndir * nrhs
+    value = units / (ms * 1e-3)
+    value_f = units / (ms_f * 1e-3)
+    n = w.n
+    # roofline of the dominant kernel of the compressed path (largest total time)
+    zname = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches"])
+    zms = kt[zname]["avg_ms"] * kt[zname]["launches"] / args.steps  # per step (one launch per step)
+    flops = restore_flops(fmt, ranks, n, ndir)
+    stored = info["bytes_stored"]
+    io = 2 * 8 * units  # A read + B written, complex64
+    # the fused kernel moves A and B as well; the three-pass z-stage only reads the operator
+    alg_bytes = stored + (io if zname.startswith("fused") else 0)
+    valu_flops = fft_flops(w.K, n, ndir, nrhs) if zname.startswith("fused") else 0.0
+    mfma_tfs = flops / (zms * 1e-3) / 1e12
+    hbm_gbs = alg_bytes / (zms * 1e-3) / 1e9
+    cand = [("mfma", mfma_tfs, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"), ("hbm", hbm_gbs, PEAK_HBM_GBS, "GB/s")]
+    if valu_flops:
+        cand.append(("alu", valu_flops / (zms * 1e-3) / 1e12, PEAK_FP32_VALU_TFLOPS, "TFLOP/s"))
+    bound = max(cand, key=lambda c: c[1] / c[2])
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            tr = json.load(open(tpath))
+            key = f"{args.workload}:{fmt}:{zname}"
+            if key in tr and tr[key].get("kernel_sha") == _kernel_sha():
+                traffic = tr[key]["bytes_per_launch"]
+        except Exception:
+            traffic = None
+    roof = {"bound": bound[0], "achieved": round(bound[1], 3), "peak": bound[2], "unit": bound[3],
+            "frac": round(bound[1] / bound[2], 4), "traffic": traffic, "kernel": zname,
+            "kernel_avg_ms": zms, "algorithmic_flops": flops, "algorithmic_bytes": alg_bytes,
+            "fft_flops": valu_flops,
+            "other_bound": {c[0]: {"achieved": round(c[1], 3), "peak": c[2], "unit": c[3],
+                                   "frac": round(c[1] / c[2], 4)} for c in cand if c[0] != bound[0]}}
+    out = {
+        "metric": "translated grid-pts*dirs/s, compressed operator (vs uncompressed), rel err <= 1e-4",
+        "value": value,
+        "unit": "grid-pts*dirs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "K": list(w.K), "box": w.box, "L": w.L, "n_dir": ndir, "fmt": fmt,
+                   "tol": w.tol, "nrhs": nrhs, "precision": w.precision},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "uncompressed": {"value": value_f, "ms_per_step": ms_f, "p50_ms": float(np.percentile(lat_f, 50)),
+                         "p99_ms": float(np.percentile(lat_f, 99)), "kernels": kt_f},
+        "time_ratio_compressed_over_full": ms / ms_f,
+        "memory_fraction": info["bytes_stored"] / finfo["bytes_stored"],
+        "op": {"ranks_max": info["ranks"], "rel_err_fro": info["rel_err_fro"], "setup_s": setup_s,
+               "bytes_stored": info["bytes_stored"], "bytes_full": finfo["bytes_stored"]},
+        "kernels": kt,
+        "fft_flops_per_step": fft_flops(w.K, n, ndir, nrhs),
+        "roofline": roof,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, fmt, gpu_B, A_np, args.cpu_seconds)
+        out["rel_err_vs_fp64"] = out["cpu_baseline"]["gpu_rel_err_max"]
+    print(json.dumps(out))
+
+
+def _kernel_sha():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "device_common.h", "gen_dft.py"):
+        with open(os.path.join(ROOT, "paper_2010_00520_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -125,7 +125,10 @@ typedef struct {
 
 /* Create a context on HIP device `device` with a device-memory budget for
  * operators and translation scratch (0 => 90% of the device's free memory).
- * Fails with TFMM_ERR_NO_DEVICE when no device is visible. */
+ * Fails with TFMM_ERR_NO_DEVICE when no device is visible.  With the
+ * environment variable TFMM_NO_FUSED=1 at creation, operators of this context
+ * always use the three-pass kernel pipeline instead of the fused
+ * one-kernel-per-direction path available for cubic grids up to 16^3 boxes. */
 tfmm_status tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx* out);
 
 /* Wait for every submitted job, stop the scheduler, free all operators and

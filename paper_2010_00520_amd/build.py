@@ -23,6 +23,7 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
+DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tt3d", "zstage_tt4d")
 
 
 def _run(cmd):
@@ -41,12 +42,14 @@ def build(verbose: bool = False) -> str:
                             os.path.join(BUILD, "host_math.o")],
         [HIPCC, "--offload-arch=" + ARCH] + COMMON + NO_PK + ["-c", os.path.join(CSRC, "api.cpp"), "-o",
                                                              os.path.join(BUILD, "api.o")],
-        [HIPCC, "--offload-arch=" + ARCH] + COMMON + NO_PK + ["-c", os.path.join(CSRC, "kernels.hip"), "-o",
-                                                             os.path.join(BUILD, "kernels.o")],
+    ] + [
+        [HIPCC, "--offload-arch=" + ARCH] + COMMON + NO_PK + ["-c", os.path.join(CSRC, f + ".hip"), "-o",
+                                                             os.path.join(BUILD, f + ".o")]
+        for f in DEVICE_UNITS
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(_run, jobs))
-    objs = [os.path.join(BUILD, n) for n in ("host_math.o", "api.o", "kernels.o")]
+    objs = [os.path.join(BUILD, n + ".o") for n in ("host_math", "api") + DEVICE_UNITS]
     tmp = LIB + ".tmp"
     _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-pthread"])
     os.replace(tmp, LIB)

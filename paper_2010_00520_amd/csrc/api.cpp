@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -74,8 +75,11 @@ struct tfmm_op_s {
   size_t dev_bytes = 0;                // bytes charged to the budget
   size_t stored_elems = 0;
   std::vector<int> desc;               // host copy of the descriptors
-  // derived plan
+  // derived plan: three-pass pipeline (cb, KC, lds) and, for small cubic
+  // grids, the fused single-kernel path (fused, fKC, flds)
   int zfmt = 0, cb = 1, KC = 8, lds = 0;
+  bool fused = false;
+  int fKC = 8, flds = 0;
   size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
   tfmm_op_info info{};
   std::atomic<int> refs{0};
@@ -105,6 +109,7 @@ struct KernelStat {
 
 struct tfmm_ctx_s {
   int device = 0;
+  bool no_fused = false;               // TFMM_NO_FUSED=1: always use the three-pass pipeline
   size_t budget = 0, used = 0;
   std::recursive_mutex mu;
   // translation scratch, one per stream slot (slot 0 = tfmm_translate; 1..S = scheduler streams)
@@ -118,7 +123,18 @@ struct tfmm_ctx_s {
     hipEvent_t a, b;
   };
   std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
   std::map<std::string, KernelStat> stats;
+  hipEvent_t take_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
   // scheduler
   hipStream_t streams[2] = {nullptr, nullptr};
   std::thread worker, completer;
@@ -244,20 +260,40 @@ tfmm_status plan_zstage(tfmm_op op) {
     default: op->zfmt = tfmm::ZF_TUCKER; break;
   }
   op->lds = 0;
-  if (op->zfmt == tfmm::ZF_FULL) return TFMM_OK;
   // largest ranks over directions bound the LDS need
   int r1 = 1, r2 = 1;
-  for (int p = 0; p < op->ndir; ++p) {
-    r1 = std::max(r1, op->desc[8 * p + 4]);
-    r2 = std::max(r2, op->desc[8 * p + 5]);
+  if (op->zfmt != tfmm::ZF_FULL)
+    for (int p = 0; p < op->ndir; ++p) {
+      r1 = std::max(r1, op->desc[8 * p + 4]);
+      r2 = std::max(r2, op->desc[8 * p + 5]);
+    }
+  const size_t lds_max = 160 * 1024;
+  if (op->zfmt != tfmm::ZF_FULL) {
+    const size_t cap = 96 * 1024;
+    int KC = 16;
+    while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2) > cap) KC /= 2;
+    size_t need = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2);
+    if (need > lds_max) return fail(TFMM_ERR_UNSUPPORTED, "ranks too large for the LDS-resident restoration");
+    op->KC = KC;
+    op->lds = (int)need;
   }
-  const size_t cap = 96 * 1024;
-  int KC = 16;
-  while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, op->cb, KC, r1, r2) > cap) KC /= 2;
-  size_t need = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, op->cb, KC, r1, r2);
-  if (need > 160 * 1024) return fail(TFMM_ERR_UNSUPPORTED, "ranks too large for the LDS-resident restoration");
-  op->KC = KC;
-  op->lds = (int)need;
+  // fused path: cubic grids whose half spectrum (n*n*zp complex64) fits in LDS
+  op->fused = false;
+  if (!op->ctx->no_fused && n1 == n2 && n2 == n3 && (n1 == 8 || n1 == 16 || n1 == 24 || n1 == 32)) {
+    const int K3 = n3 / 2, zp = (K3 & 1) ? K3 : K3 + 1;
+    const size_t hbytes = (size_t)n1 * n2 * zp * sizeof(float2);
+    int KC = 16;
+    size_t rb = 0;
+    if (op->zfmt != tfmm::ZF_FULL) {
+      while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2) > lds_max) KC /= 2;
+      rb = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2);
+    }
+    if (hbytes <= lds_max && rb <= lds_max) {
+      op->fused = true;
+      op->fKC = KC;
+      op->flds = (int)std::max(hbytes, rb);
+    }
+  }
   return TFMM_OK;
 }
 
@@ -432,14 +468,13 @@ struct Launch {
   const char* name;
   Launch(tfmm_ctx c_, hipStream_t s, const char* n) : c(c_), st(s), name(n) {
     if (c->prof) {
-      (void)hipEventCreate(&a);
+      a = c->take_event();
       (void)hipEventRecord(a, st);
     }
   }
   void done() {
     if (c->prof) {
-      hipEvent_t b;
-      (void)hipEventCreate(&b);
+      hipEvent_t b = c->take_event();
       (void)hipEventRecord(b, st);
       c->pending.push_back({name, a, b});
     }
@@ -503,7 +538,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   const size_t hcap = (size_t)256 << 20;  // half-spectrum scratch per chunk
   const int rhs_group = std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH);
   int ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, hcap / (per_dir_rhs * rhs_group)));
-  const size_t hbytes = per_dir_rhs * rhs_group * ndl;
+  const size_t hbytes = op->fused ? 0 : per_dir_rhs * rhs_group * ndl;
   void* scr = nullptr;
   tfmm_status s = ensure_scratch(c, slot, hbytes + op->a1_bytes, &scr);
   if (s != TFMM_OK) return s;
@@ -532,6 +567,27 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   z.cb = op->cb;
   z.lds_bytes = op->lds;
   const float scale = 1.0f / (float)((double)n1 * n2 * n3);
+  if (op->fused) {
+    z.KC = op->fKC;
+    z.lds_bytes = op->flds;
+    z.p0 = 0;
+    z.ndl = nd;
+    for (int r0 = 0; r0 < nr_total; r0 += rhs_group) {
+      const int nr = std::min(rhs_group, nr_total - r0);
+      tfmm::RhsPtrs P{};
+      for (int i = 0; i < nr; ++i) {
+        P.a[i] = As[r0 + i];
+        P.b[i] = Bs[r0 + i];
+      }
+      z.nrhs = nr;
+      bool ok = false;
+      Launch L(c, st, op->zfmt == tfmm::ZF_FULL ? "fused_full" : "fused_restore");
+      HIP_TRY(tfmm::launch_fused(z, P, scale, st, &ok));
+      L.done();
+      if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "fused translation size unsupported");
+    }
+    return TFMM_OK;
+  }
   for (int r0 = 0; r0 < nr_total; r0 += rhs_group) {
     const int nr = std::min(rhs_group, nr_total - r0);
     tfmm::RhsPtrs P{};
@@ -716,6 +772,8 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   tfmm_ctx c = new tfmm_ctx_s();
   c->device = device;
   c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+  const char* nf = std::getenv("TFMM_NO_FUSED");
+  c->no_fused = nf && nf[0] == '1';
   for (int i = 0; i < 2; ++i)
     if (hipStreamCreateWithFlags(&c->streams[i], hipStreamNonBlocking) != hipSuccess) {
       delete c;
@@ -744,6 +802,7 @@ tfmm_status tfmm_ctx_destroy(tfmm_ctx c) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
   }
+  for (auto e : c->event_pool) (void)hipEventDestroy(e);
   for (tfmm_op op : c->ops) free_op(c, op);
   for (auto& kv : c->roots) (void)hipFree(kv.second);
   for (auto& s : c->scratch)
@@ -997,14 +1056,15 @@ tfmm_status tfmm_kernel_times(tfmm_ctx c, char* names, size_t names_cap, double*
       c->stats[p.name].total_ms += ms;
       c->stats[p.name].n += 1;
     }
-    (void)hipEventDestroy(p.a);
-    (void)hipEventDestroy(p.b);
+    c->event_pool.push_back(p.a);
+    c->event_pool.push_back(p.b);
   }
   c->pending.clear();
   int i = 0;
+  const int lim = cap < 0 ? -cap : cap;
   std::string joined;
   for (auto& kv : c->stats) {
-    if (i < cap) {
+    if (i < lim) {
       if (avg_ms) avg_ms[i] = kv.second.n ? kv.second.total_ms / kv.second.n : 0.0;
       if (launches) launches[i] = kv.second.n;
     }

@@ -35,13 +35,14 @@ struct LOp {
 // tile covers 8 complex rows (re/im interleaved) x 16 complex columns, the
 // real K index is (k, re/im) so one 16x16x4 MFMA step consumes 2 complex k.
 // Every wave walks its share of the tiles; all lanes take part in each MFMA.
+template <int NW>
 __device__ __forceinline__ void block_cgemm(float2* lds, int M, int N, int K, int nb, LOp A, LOp B, LOp C) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int tmN = (M + 7) >> 3, tnN = (N + 15) >> 4;
   const int per = tmN * tnN, ntiles = nb * per;
   const int ks = (K + 1) >> 1;
   const int kofs = (l >> 4) >> 1, ki = (l >> 4) & 1, ari = l & 1;
-  for (int tile = w; tile < ntiles; tile += TFMM_NWAVES) {
+  for (int tile = w; tile < ntiles; tile += NW) {
     const int bat = tile / per, rem = tile - bat * per;
     const int tm = rem / tnN, tn = rem - tm * tnN;
     const int am = tm * 8 + ((l & 15) >> 1);

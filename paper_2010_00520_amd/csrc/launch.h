@@ -29,8 +29,9 @@ struct ZArgs {
   int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
 };
 
-// LDS bytes the z-stage needs for a format / ranks / chunk (host-side planning).
-size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int cb, int KC, int r1, int r2);
+// LDS bytes a restoration of a qt-pencil tile needs for a format / ranks /
+// chunk (host-side planning; qt = n1*n2 for the fused kernel).
+size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1, int r2);
 
 // Per-RHS base pointers of one launch: rhs s reads A_s[n_dir][Kx][Ky][Kz] and
 // writes B_s of the same shape (complex64).  Passed by value.
@@ -45,6 +46,17 @@ hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, in
 hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
                          float scale, hipStream_t st, bool* supported);
 hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported);
+
+// Fused single-kernel translation (one block per direction) for cubic grids
+// n in {8, 16, 24, 32}; a.lds_bytes must cover both the restoration and the
+// half spectrum n*n*(n/2 | 1) complex64.
+hipError_t launch_fused(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_t st, bool* supported);
+
+// Per-family instantiations (zstage_<family>.hip).
+template <int FMT>
+hipError_t launch_zstage_fmt(const ZArgs& a, hipStream_t st, bool* supported);
+template <int FMT>
+hipError_t launch_fused_fmt(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_t st, bool* supported);
 
 // Batched complex GEMM on global memory: C_b[m][n] = sum_k A_b[m][k] B_b[k][n],
 // element (i, j, b) of X at X.p + i*s0 + j*s1 + b*sb (float2 units).

@@ -1,0 +1,373 @@
+// Device stages of the translation (Eq. (5) with on-the-fly restoration) and
+// the kernels built from them.  Included by one translation unit per operator
+// family so the template instantiations compile in parallel.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "launch.h"
+#include "xy_stages.h"
+
+namespace tfmm {
+
+// ---------------------------------------------------------------------------
+// Restoration of an operator tile into MFMA accumulators.
+//
+// Accumulator layout (16x16x4 f32 MFMA, D[i][j] in lane j + 16*(i/4), reg i%4):
+// real row R = 16 t + 4 g + r of row tile t is (fz, re/im) = (8t + 2g + r/2,
+// r%2); column j of column block c is pencil q0 + (w*CB + c)*16 + j.  The tile
+// is T~_p[fz][q] = sum_k V[fz][k] W[q][k] (V = U3, or the TT-4D direction slice;
+// W = the pencil-side partial contraction), accumulated chunk by chunk of k.
+// ---------------------------------------------------------------------------
+template <int T, int CB>
+__device__ __forceinline__ void restore_final_chunk(v4f (&acc)[T][CB], const float2* sV, const float2* sW, int KC,
+                                                    int kc) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15;
+  const int kofs = (l >> 4) >> 1, ki = (l >> 4) & 1, ri = l & 1;
+  const int ks = (kc + 1) >> 1;
+  for (int s = 0; s < ks; ++s) {
+    const int k = 2 * s + kofs;
+    const bool kok = k < kc;
+    float av[T], bv[CB];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int fz = 8 * t + (j >> 1);
+      const float2 v = kok ? sV[fz * KC + k] : make_float2(0.f, 0.f);
+      av[t] = ri == 0 ? (ki == 0 ? v.x : -v.y) : (ki == 0 ? v.y : v.x);
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int ql = (w * CB + c) * 16 + j;
+      const float2 v = kok ? sW[ql * KC + k] : make_float2(0.f, 0.f);
+      bv[c] = ki == 0 ? v.x : v.y;
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[t][c] = mfma4(av[t], bv[c], acc[t][c]);
+  }
+}
+
+template <int FMT, int T, int CB, int NW>
+__device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, int p, int q0, float2* lds) {
+  constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+  const int tid = threadIdx.x;
+  const int nq = a.nq, n2 = a.n2;
+#pragma unroll
+  for (int t = 0; t < T; ++t)
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[t][c] = v4f{0.f, 0.f, 0.f, 0.f};
+  if constexpr (FMT == ZF_FULL) {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int q = q0 + (w * CB + c) * 16 + j;
+        if (q < nq) {
+          const float4 v = a.Tfull[((long long)p * (N3 / 2) + 4 * t + g) * nq + q];
+          acc[t][c] = v4f{v.x, v.y, v.z, v.w};
+        }
+      }
+  } else {
+    const int* d = a.desc + 8 * p;
+    const int KC = a.KC;
+    if constexpr (FMT == ZF_TUCKER) {
+      const int r1 = d[4], r2 = d[5], r3 = d[6];
+      const float2* C = a.cbase + d[0];
+      const float2* U1 = a.fbase + d[1];
+      const float2* U2 = a.fbase + d[2];
+      const float2* U3 = a.fbase + d[3];
+      const int nfx = QT / n2, fx0 = q0 / n2;
+      const int oU1 = 0, oU2 = oU1 + nfx * r1, oC = oU2 + n2 * r2, oW1 = oC + r1 * r2 * KC,
+                oW = oW1 + nfx * r2 * KC, oV = oW + QT * KC;
+      for (int e = tid; e < nfx * r1; e += NT) lds[oU1 + e] = U1[fx0 * r1 + e];
+      for (int e = tid; e < n2 * r2; e += NT) lds[oU2 + e] = U2[e];
+      for (int c0 = 0; c0 < r3; c0 += KC) {
+        const int kc = min(KC, r3 - c0);
+        for (int e = tid; e < r1 * r2 * KC; e += NT) {
+          const int cl = e % KC, ab = e / KC;
+          lds[oC + e] = cl < kc ? C[(long long)ab * r3 + c0 + cl] : make_float2(0.f, 0.f);
+        }
+        for (int e = tid; e < N3 * KC; e += NT) {
+          const int cl = e % KC, fz = e / KC;
+          lds[oV + e] = cl < kc ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        // W1[fx][(b,cl)] = sum_a U1[fx][a] C[a][(b,cl)]             (Fig. 3(a) step 1)
+        block_cgemm<NW>(lds, nfx, r2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, r2 * KC, 1, 0},
+                        LOp{oW1, r2 * KC, 1, 0});
+        __syncthreads();
+        // W[(fx,fy)][cl] = sum_b W1[fx][b][cl] U2[fy][b]              (step 2), batch over cl
+        block_cgemm<NW>(lds, nfx, n2, r2, kc, LOp{oW1, r2 * KC, KC, 1}, LOp{oU2, 1, r2, 0},
+                        LOp{oW, n2 * KC, KC, 1});
+        __syncthreads();
+        // T~[fz][q] += sum_c U3[fz][c] W[q][c]                         (step 3)
+        restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);
+        __syncthreads();
+      }
+    } else if constexpr (FMT == ZF_TT3D) {
+      const int r1 = d[4], r2 = d[5];
+      const float2* C = a.cbase + d[0];
+      const float2* U1 = a.fbase + d[1];
+      const float2* U3 = a.fbase + d[3];
+      const int nfx = QT / n2, fx0 = q0 / n2;
+      const int oU1 = 0, oC = oU1 + nfx * r1, oW = oC + r1 * n2 * KC, oV = oW + QT * KC;
+      for (int e = tid; e < nfx * r1; e += NT) lds[oU1 + e] = U1[fx0 * r1 + e];
+      for (int b0 = 0; b0 < r2; b0 += KC) {
+        const int kc = min(KC, r2 - b0);
+        for (int e = tid; e < r1 * n2 * KC; e += NT) {
+          const int bl = e % KC, ay = e / KC;
+          lds[oC + e] = bl < kc ? C[(long long)ay * r2 + b0 + bl] : make_float2(0.f, 0.f);
+        }
+        for (int e = tid; e < N3 * KC; e += NT) {
+          const int bl = e % KC, fz = e / KC;
+          lds[oV + e] = bl < kc ? U3[fz * r2 + b0 + bl] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        // W[(fx,fy)][bl] = sum_a U1[fx][a] C[a][(fy,bl)]              (Fig. 4(a) step 1)
+        block_cgemm<NW>(lds, nfx, n2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, n2 * KC, 1, 0},
+                        LOp{oW, n2 * KC, 1, 0});
+        __syncthreads();
+        restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);  // step 2
+        __syncthreads();
+      }
+    } else {  // ZF_TT4D: W = T1 (direction-independent), V = S_p (Fig. 4(b))
+      const int r2 = d[5];
+      const float2* V = a.vbase + d[3];
+      const int oW = 0, oV = QT * KC;
+      for (int b0 = 0; b0 < r2; b0 += KC) {
+        const int kc = min(KC, r2 - b0);
+        for (int e = tid; e < QT * KC; e += NT) {
+          const int bl = e % KC, ql = e / KC;
+          const int q = q0 + ql;
+          lds[oW + e] = (bl < kc && q < nq) ? a.wbase[(long long)q * r2 + b0 + bl] : make_float2(0.f, 0.f);
+        }
+        for (int e = tid; e < N3 * KC; e += NT) {
+          const int bl = e % KC, fz = e / KC;
+          lds[oV + e] = bl < kc ? V[fz * r2 + b0 + bl] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z-FFT, product and inverse z-FFT of one RHS in the accumulator layout.
+// Lane (g, j) owns fz = 8t + b, b in {2g, 2g+1}, t < T (n3 = 8T):
+//   forward  X[8t+b] = DFT_T over v of  w^{vb} sum_{u<4} x[Tu+v] w8^{ub}
+//   inverse  out[Tu'+v'] = sum_b w8^{-bu'} w^{-bv'} IDFT_T over t of Y[8t+b]
+// (w = exp(-2 pi i/n3), w8 = exp(-2 pi i/8)).  The inverse partial sums of the
+// four lane groups are reduce-scattered with two cross-lane exchanges, after
+// which lane group g holds out[z'] for z' in [T g, T g + T).
+// Element (z, q) of the half spectrum is at H[z*zs + q*qs].
+// ---------------------------------------------------------------------------
+template <int T>
+__device__ __forceinline__ void dft_small_fwd(const float2* x, float2* y) {
+  if constexpr (T == 1) dft_full_fwd_1(x, y);
+  else if constexpr (T == 2) dft_full_fwd_2(x, y);
+  else if constexpr (T == 3) dft_full_fwd_3(x, y);
+  else if constexpr (T == 4) dft_full_fwd_4(x, y);
+  else if constexpr (T == 6) dft_full_fwd_6(x, y);
+  else dft_full_fwd_8(x, y);
+}
+template <int T>
+__device__ __forceinline__ void dft_small_inv(const float2* x, float2* y) {
+  if constexpr (T == 1) dft_full_inv_1(x, y);
+  else if constexpr (T == 2) dft_full_inv_2(x, y);
+  else if constexpr (T == 3) dft_full_inv_3(x, y);
+  else if constexpr (T == 4) dft_full_inv_4(x, y);
+  else if constexpr (T == 6) dft_full_inv_6(x, y);
+  else dft_full_inv_8(x, y);
+}
+
+__device__ __forceinline__ float2 shfl_xor2(float2 v, int mask) {
+  return make_float2(__shfl_xor(v.x, mask), __shfl_xor(v.y, mask));
+}
+
+template <int T>
+struct ZTwiddles {
+  float2 tw[2][T], w8[4][2];
+  __device__ __forceinline__ void load(const float2* roots) {
+    constexpr int N3 = 8 * T;
+    const int g = (threadIdx.x & 63) >> 4;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int b = 2 * g + e;
+#pragma unroll
+      for (int v = 0; v < T; ++v) tw[e][v] = roots[(v * b) % N3];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w8[u][e] = roots[(u * b * T) % N3];
+    }
+  }
+};
+
+template <int T, int CB>
+__device__ __forceinline__ void zfft_rhs(const v4f (&acc)[T][CB], float2* H, long long zs, int qs, int qbase, int nq,
+                                         const ZTwiddles<T>& Z) {
+  constexpr int KZ = 4 * T;
+  const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+  const bool hi = g >= 2, odd = (g & 1) != 0;
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int q = qbase + c * 16 + j;
+    const bool qok = q < nq;
+    float2 x[KZ];
+#pragma unroll
+    for (int z = 0; z < KZ; ++z) x[z] = qok ? H[z * zs + (long long)q * qs] : make_float2(0.f, 0.f);
+    float2 zt[2][T];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      float2 yv[T], X[T], Y[T], Zi[T];
+#pragma unroll
+      for (int v = 0; v < T; ++v) {
+        float2 sacc = x[v];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) sacc = cadd(sacc, cmul(x[T * u + v], Z.w8[u][e]));
+        yv[v] = cmul(sacc, Z.tw[e][v]);
+      }
+      dft_small_fwd<T>(yv, X);
+#pragma unroll
+      for (int t = 0; t < T; ++t) Y[t] = cmul(X[t], make_float2(acc[t][c][2 * e], acc[t][c][2 * e + 1]));
+      dft_small_inv<T>(Y, Zi);
+#pragma unroll
+      for (int v = 0; v < T; ++v) zt[e][v] = cmulconj(Zi[v], Z.tw[e][v]);
+    }
+    float2 kept[2][T];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int v = 0; v < T; ++v) {
+        const float2 plo = cadd(cmulconj(zt[0][v], Z.w8[k][0]), cmulconj(zt[1][v], Z.w8[k][1]));
+        const float2 phi = cadd(cmulconj(zt[0][v], Z.w8[2 + k][0]), cmulconj(zt[1][v], Z.w8[2 + k][1]));
+        kept[k][v] = cadd(hi ? phi : plo, shfl_xor2(hi ? plo : phi, 32));
+      }
+#pragma unroll
+    for (int v = 0; v < T; ++v) {
+      const float2 out = cadd(odd ? kept[1][v] : kept[0][v], shfl_xor2(odd ? kept[0][v] : kept[1][v], 16));
+      if (qok) H[(T * g + v) * zs + (long long)q * qs] = out;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2 of the three-pass pipeline: one block per (pencil tile, direction);
+// the restored tile is shared by every RHS of the launch.
+// ---------------------------------------------------------------------------
+template <int FMT, int T, int CB>
+__global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
+  extern __shared__ float2 lds[];
+  constexpr int NW = 4, QT = 16 * CB * NW;
+  const int w = threadIdx.x >> 6;
+  const int q0 = blockIdx.x * QT;
+  const int pl = blockIdx.y, p = a.p0 + pl;
+  v4f acc[T][CB];
+  restore_tile<FMT, T, CB, NW>(acc, a, p, q0, lds);
+  ZTwiddles<T> Z;
+  Z.load(a.roots);
+  for (int s = 0; s < a.nrhs; ++s) {
+    float2* Hs = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq);
+    zfft_rhs<T, CB>(acc, Hs, a.nq, 1, q0 + w * CB * 16, a.nq, Z);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused translation for grids whose half spectrum fits in LDS: one block per
+// direction restores the whole T~_p into accumulators once, then for every RHS
+// runs the xy-FFTs, the z-stage and the inverse xy-FFTs on chip.  A and B are
+// the only device-memory traffic besides the stored operator.
+// ---------------------------------------------------------------------------
+template <int FMT, int N, int NW, int CB>
+__global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float scale) {
+  extern __shared__ float2 lds[];
+  constexpr int T = N / 8, K = N / 2, NQ = N * N, NT = 64 * NW;
+  constexpr int ZP = (K & 1) ? K : K + 1;
+  static_assert(NQ == 16 * CB * NW, "tile must cover every pencil");
+  const int w = threadIdx.x >> 6;
+  const int p = a.p0 + blockIdx.x;
+  v4f acc[T][CB];
+  restore_tile<FMT, T, CB, NW>(acc, a, p, 0, lds);
+  ZTwiddles<T> Z;
+  Z.load(a.roots);
+  __syncthreads();
+  const long long blk = (long long)K * K * K;
+  for (int s = 0; s < a.nrhs; ++s) {
+    xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0);
+    __syncthreads();
+    zfft_rhs<T, CB>(acc, lds, 1, ZP, w * CB * 16, NQ, Z);
+    __syncthreads();
+    xy_inverse<N, N, NT>(lds, P.b[s] + (long long)p * blk, K, K, ZP, 0, scale);
+    __syncthreads();
+  }
+}
+
+// fused shape per grid: (waves, column blocks)
+template <int N> struct FusedShape;
+template <> struct FusedShape<8> { static constexpr int NW = 4, CB = 1; };
+template <> struct FusedShape<16> { static constexpr int NW = 8, CB = 2; };
+template <> struct FusedShape<24> { static constexpr int NW = 6, CB = 6; };
+template <> struct FusedShape<32> { static constexpr int NW = 8, CB = 8; };
+
+template <int FMT, int T, int CB>
+hipError_t run_zstage(const ZArgs& a, hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_zstage<FMT, T, CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  dim3 grid(a.nq / (64 * CB), a.ndl);
+  hipLaunchKernelGGL((k_zstage<FMT, T, CB>), grid, dim3(256), (size_t)a.lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+template <int FMT, int N>
+hipError_t run_fused(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_t st) {
+  constexpr int NW = FusedShape<N>::NW, CB = FusedShape<N>::CB;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_fused<FMT, N, NW, CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB>), dim3(a.ndl), dim3(64 * NW), (size_t)a.lds_bytes, st, a, P, scale);
+  return hipGetLastError();
+}
+
+template <int FMT>
+hipError_t launch_zstage_fmt(const ZArgs& a, hipStream_t st, bool* supported) {
+  *supported = true;
+  switch ((a.n3 / 8) * 10 + a.cb) {
+#define ZC(TT, C) \
+  case TT * 10 + C: return run_zstage<FMT, TT, C>(a, st);
+    ZC(1, 1) ZC(1, 2) ZC(1, 3) ZC(1, 4)
+    ZC(2, 1) ZC(2, 2) ZC(2, 3) ZC(2, 4)
+    ZC(3, 1) ZC(3, 2) ZC(3, 3) ZC(3, 4)
+    ZC(4, 1) ZC(4, 2) ZC(4, 3) ZC(4, 4)
+    ZC(6, 1) ZC(6, 2) ZC(6, 3)
+    ZC(8, 1) ZC(8, 2)
+#undef ZC
+  }
+  *supported = false;
+  return hipSuccess;
+}
+
+template <int FMT>
+hipError_t launch_fused_fmt(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_t st, bool* supported) {
+  *supported = true;
+  if (a.n1 == a.n2 && a.n2 == a.n3) {
+    switch (a.n1) {
+      case 8: return run_fused<FMT, 8>(a, P, scale, st);
+      case 16: return run_fused<FMT, 16>(a, P, scale, st);
+      case 24: return run_fused<FMT, 24>(a, P, scale, st);
+      case 32: return run_fused<FMT, 32>(a, P, scale, st);
+    }
+  }
+  *supported = false;
+  return hipSuccess;
+}
+
+}  // namespace tfmm
