@@ -34,41 +34,71 @@ struct LOp {
 // The complex product is embedded in real arithmetic: a 16 x 16 real output
 // tile covers 8 complex rows (re/im interleaved) x 16 complex columns, the
 // real K index is (k, re/im) so one 16x16x4 MFMA step consumes 2 complex k.
-// Every wave walks its share of the tiles; all lanes take part in each MFMA.
+// Every wave walks its share of the work in units of one 8-row x 32-column
+// block (two output tiles sharing the A fragment); the K loop is unrolled by
+// four with all operand loads issued before the MFMAs that consume them.
+__device__ __forceinline__ float embed_a(float2 v, int ri, int ki) {
+  // real embedding of a complex A entry: [[re, -im], [im, re]]
+  return ri == 0 ? (ki == 0 ? v.x : -v.y) : (ki == 0 ? v.y : v.x);
+}
+
 template <int NW>
 __device__ __forceinline__ void block_cgemm(float2* lds, int M, int N, int K, int nb, LOp A, LOp B, LOp C) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int tmN = (M + 7) >> 3, tnN = (N + 15) >> 4;
-  const int per = tmN * tnN, ntiles = nb * per;
+  const int tmN = (M + 7) >> 3, tpN = (N + 31) >> 5;
+  const int per = tmN * tpN, ntiles = nb * per;
   const int ks = (K + 1) >> 1;
   const int kofs = (l >> 4) >> 1, ki = (l >> 4) & 1, ari = l & 1;
   for (int tile = w; tile < ntiles; tile += NW) {
     const int bat = tile / per, rem = tile - bat * per;
-    const int tm = rem / tnN, tn = rem - tm * tnN;
+    const int tm = rem / tpN, tp = rem - tm * tpN;
     const int am = tm * 8 + ((l & 15) >> 1);
-    const int bn = tn * 16 + (l & 15);
-    const bool aok = am < M, bok = bn < N;
-    const float2* ap = lds + A.off + am * A.s0 + bat * A.sb;
-    const float2* bp = lds + B.off + bn * B.s1 + bat * B.sb;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < ks; ++s) {
-      const int k = 2 * s + kofs;
-      float a = 0.f, b = 0.f;
-      if (aok && k < K) {
-        const float2 v = ap[k * A.s1];
-        a = ari == 0 ? (ki == 0 ? v.x : -v.y) : (ki == 0 ? v.y : v.x);
+    const int bn0 = tp * 32 + (l & 15), bn1 = bn0 + 16;
+    const bool aok = am < M, b0ok = bn0 < N, b1ok = bn1 < N;
+    const float2* ap = lds + A.off + (aok ? am : 0) * A.s0 + bat * A.sb;
+    const float2* bp0 = lds + B.off + (b0ok ? bn0 : 0) * B.s1 + bat * B.sb;
+    const float2* bp1 = lds + B.off + (b1ok ? bn1 : 0) * B.s1 + bat * B.sb;
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    int s = 0;
+    for (; s + 4 <= ks; s += 4) {
+      float ar[4], ai[4], b0r[4], b0i[4], b1r[4], b1i[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int k = 2 * (s + u) + kofs;
+        const bool kok = k < K;
+        const float2 va = (aok && kok) ? ap[k * A.s1] : make_float2(0.f, 0.f);
+        const float2 vb0 = (b0ok && kok) ? bp0[k * B.s0] : make_float2(0.f, 0.f);
+        const float2 vb1 = (b1ok && kok) ? bp1[k * B.s0] : make_float2(0.f, 0.f);
+        ar[u] = va.x; ai[u] = va.y;
+        b0r[u] = vb0.x; b0i[u] = vb0.y;
+        b1r[u] = vb1.x; b1i[u] = vb1.y;
       }
-      if (bok && k < K) {
-        const float2 v = bp[k * B.s0];
-        b = ki == 0 ? v.x : v.y;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float a = embed_a(make_float2(ar[u], ai[u]), ari, ki);
+        acc0 = mfma4(a, ki == 0 ? b0r[u] : b0i[u], acc0);
+        acc1 = mfma4(a, ki == 0 ? b1r[u] : b1i[u], acc1);
       }
-      acc = mfma4(a, b, acc);
     }
-    const int cn = tn * 16 + (l & 15), cm0 = tm * 8 + 2 * (l >> 4);
-    if (cn < N) {
-      float2* cp = lds + C.off + cn * C.s1 + bat * C.sb;
-      if (cm0 < M) cp[cm0 * C.s0] = make_float2(acc[0], acc[1]);
-      if (cm0 + 1 < M) cp[(cm0 + 1) * C.s0] = make_float2(acc[2], acc[3]);
+    for (; s < ks; ++s) {
+      const int k = 2 * s + kofs;
+      const bool kok = k < K;
+      const float2 va = (aok && kok) ? ap[k * A.s1] : make_float2(0.f, 0.f);
+      const float2 vb0 = (b0ok && kok) ? bp0[k * B.s0] : make_float2(0.f, 0.f);
+      const float2 vb1 = (b1ok && kok) ? bp1[k * B.s0] : make_float2(0.f, 0.f);
+      const float a = embed_a(va, ari, ki);
+      acc0 = mfma4(a, ki == 0 ? vb0.x : vb0.y, acc0);
+      acc1 = mfma4(a, ki == 0 ? vb1.x : vb1.y, acc1);
+    }
+    const int cm0 = tm * 8 + 2 * (l >> 4);
+    float2* cb = lds + C.off + bat * C.sb;
+    if (b0ok) {
+      if (cm0 < M) cb[cm0 * C.s0 + bn0 * C.s1] = make_float2(acc0[0], acc0[1]);
+      if (cm0 + 1 < M) cb[(cm0 + 1) * C.s0 + bn0 * C.s1] = make_float2(acc0[2], acc0[3]);
+    }
+    if (b1ok) {
+      if (cm0 < M) cb[cm0 * C.s0 + bn1 * C.s1] = make_float2(acc1[0], acc1[1]);
+      if (cm0 + 1 < M) cb[(cm0 + 1) * C.s0 + bn1 * C.s1] = make_float2(acc1[2], acc1[3]);
     }
   }
 }

@@ -48,6 +48,44 @@ __device__ __forceinline__ void restore_final_chunk(v4f (&acc)[T][CB], const flo
   }
 }
 
+// A chunk of a factor copied to LDS: element e (row e >> kcs, column e & (KC-1))
+// is base[row*rstride + c0 + col] for col < kc and row < rows, else zero.
+struct ChunkSrc {
+  const float2* base;
+  int rstride, rows, kcs, KC;
+  __device__ __forceinline__ float2 at(int e, int c0, int kc) const {
+    const int col = e & (KC - 1), row = e >> kcs;
+    return (col < kc && row < rows) ? base[(long long)row * rstride + c0 + col] : make_float2(0.f, 0.f);
+  }
+};
+
+// Register prefetch of the next chunk: its first PF*NT elements are loaded
+// into registers while the current chunk is consumed (block barriers only
+// drain LDS traffic, so the loads stay in flight); the rest is loaded at
+// store time.
+template <int NT>
+struct ChunkPrefetch {
+  static constexpr int PF = 8;
+  float rx[PF], ry[PF];
+  __device__ __forceinline__ void load(const ChunkSrc& src, int count, int c0, int kc) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = threadIdx.x + i * NT;
+      const float2 v = e < count ? src.at(e, c0, kc) : make_float2(0.f, 0.f);
+      rx[i] = v.x;
+      ry[i] = v.y;
+    }
+  }
+  __device__ __forceinline__ void store(float2* dst, const ChunkSrc& src, int count, int c0, int kc) {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < count) dst[e] = make_float2(rx[i], ry[i]);
+    }
+    for (int e = threadIdx.x + PF * NT; e < count; e += NT) dst[e] = src.at(e, c0, kc);
+  }
+};
+
 template <int FMT, int T, int CB, int NW>
 __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, int p, int q0, float2* lds) {
   constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T;
@@ -71,7 +109,7 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       }
   } else {
     const int* d = a.desc + 8 * p;
-    const int KC = a.KC;
+    const int KC = a.KC, kcs = 31 - __builtin_clz(KC);  // KC is a power of two
     if constexpr (FMT == ZF_TUCKER) {
       const int r1 = d[4], r2 = d[5], r3 = d[6];
       const float2* C = a.cbase + d[0];
@@ -83,17 +121,20 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
                 oW = oW1 + nfx * r2 * KC, oV = oW + QT * KC;
       for (int e = tid; e < nfx * r1; e += NT) lds[oU1 + e] = U1[fx0 * r1 + e];
       for (int e = tid; e < n2 * r2; e += NT) lds[oU2 + e] = U2[e];
+      // core chunk element e = (a*r2 + b)*KC + cl  <-  C[a][b][c0 + cl]
+      const int csz = r1 * r2 * KC;
+      const ChunkSrc src{C, r3, r1 * r2, kcs, KC};
+      ChunkPrefetch<NT> pf;
+      pf.load(src, csz, 0, min(KC, r3));
       for (int c0 = 0; c0 < r3; c0 += KC) {
         const int kc = min(KC, r3 - c0);
-        for (int e = tid; e < r1 * r2 * KC; e += NT) {
-          const int cl = e % KC, ab = e / KC;
-          lds[oC + e] = cl < kc ? C[(long long)ab * r3 + c0 + cl] : make_float2(0.f, 0.f);
-        }
+        pf.store(lds + oC, src, csz, c0, kc);
         for (int e = tid; e < N3 * KC; e += NT) {
-          const int cl = e % KC, fz = e / KC;
+          const int cl = e & (KC - 1), fz = e >> kcs;
           lds[oV + e] = cl < kc ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f);
         }
         __syncthreads();
+        if (c0 + KC < r3) pf.load(src, csz, c0 + KC, min(KC, r3 - c0 - KC));
         // W1[fx][(b,cl)] = sum_a U1[fx][a] C[a][(b,cl)]             (Fig. 3(a) step 1)
         block_cgemm<NW>(lds, nfx, r2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, r2 * KC, 1, 0},
                         LOp{oW1, r2 * KC, 1, 0});
@@ -114,17 +155,20 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       const int nfx = QT / n2, fx0 = q0 / n2;
       const int oU1 = 0, oC = oU1 + nfx * r1, oW = oC + r1 * n2 * KC, oV = oW + QT * KC;
       for (int e = tid; e < nfx * r1; e += NT) lds[oU1 + e] = U1[fx0 * r1 + e];
+      // core chunk element e = (a*n2 + y)*KC + bl  <-  C[a][y][b0 + bl]
+      const int csz = r1 * n2 * KC;
+      const ChunkSrc src{C, r2, r1 * n2, kcs, KC};
+      ChunkPrefetch<NT> pf;
+      pf.load(src, csz, 0, min(KC, r2));
       for (int b0 = 0; b0 < r2; b0 += KC) {
         const int kc = min(KC, r2 - b0);
-        for (int e = tid; e < r1 * n2 * KC; e += NT) {
-          const int bl = e % KC, ay = e / KC;
-          lds[oC + e] = bl < kc ? C[(long long)ay * r2 + b0 + bl] : make_float2(0.f, 0.f);
-        }
+        pf.store(lds + oC, src, csz, b0, kc);
         for (int e = tid; e < N3 * KC; e += NT) {
-          const int bl = e % KC, fz = e / KC;
+          const int bl = e & (KC - 1), fz = e >> kcs;
           lds[oV + e] = bl < kc ? U3[fz * r2 + b0 + bl] : make_float2(0.f, 0.f);
         }
         __syncthreads();
+        if (b0 + KC < r2) pf.load(src, csz, b0 + KC, min(KC, r2 - b0 - KC));
         // W[(fx,fy)][bl] = sum_a U1[fx][a] C[a][(fy,bl)]              (Fig. 4(a) step 1)
         block_cgemm<NW>(lds, nfx, n2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, n2 * KC, 1, 0},
                         LOp{oW, n2 * KC, 1, 0});
@@ -136,18 +180,20 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       const int r2 = d[5];
       const float2* V = a.vbase + d[3];
       const int oW = 0, oV = QT * KC;
+      // W chunk element e = ql*KC + bl  <-  T1[q0 + ql][b0 + bl]
+      const int wsz = QT * KC;
+      const ChunkSrc src{a.wbase + (long long)q0 * r2, r2, nq - q0, kcs, KC};
+      ChunkPrefetch<NT> pf;
+      pf.load(src, wsz, 0, min(KC, r2));
       for (int b0 = 0; b0 < r2; b0 += KC) {
         const int kc = min(KC, r2 - b0);
-        for (int e = tid; e < QT * KC; e += NT) {
-          const int bl = e % KC, ql = e / KC;
-          const int q = q0 + ql;
-          lds[oW + e] = (bl < kc && q < nq) ? a.wbase[(long long)q * r2 + b0 + bl] : make_float2(0.f, 0.f);
-        }
+        pf.store(lds + oW, src, wsz, b0, kc);
         for (int e = tid; e < N3 * KC; e += NT) {
-          const int bl = e % KC, fz = e / KC;
+          const int bl = e & (KC - 1), fz = e >> kcs;
           lds[oV + e] = bl < kc ? V[fz * r2 + b0 + bl] : make_float2(0.f, 0.f);
         }
         __syncthreads();
+        if (b0 + KC < r2) pf.load(src, wsz, b0 + KC, min(KC, r2 - b0 - KC));
         restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);
         __syncthreads();
       }
