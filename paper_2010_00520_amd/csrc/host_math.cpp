@@ -339,7 +339,9 @@ Basis basis_from_gram(std::vector<cd> G, int D, double budget2) {
   std::vector<cd> vecs;
   hermitian_eig(D, G, vals, vecs);
   double lmax = vals.empty() ? 0.0 : std::max(0.0, vals[0]);
-  double margin = 64.0 * 2.2e-16 * lmax * std::sqrt((double)D);
+  // Eigenvalues of the FP64 Gram carry an absolute error of a few eps * lambda_max;
+  // count that against the budget for every discarded value.
+  double margin = 4.0 * 2.2e-16 * lmax;
   Basis b;
   b.r = truncation_rank(vals, budget2, margin);
   b.U.resize((size_t)D * b.r);
