@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--workload", default="plain", choices=["plain", "batching", "precision", "tiny", "serving"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests in the stream")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run 10 plain device copies of MIB MiB (reference for HBM byte counters)")
     ap.add_argument("--fmt", default=None, help="override the compressed format")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -276,6 +278,14 @@ def main():
     fmt = args.fmt or w.fmt
     A_np = synth.patterns_for(w)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 18  # MiB -> float32 count
+        src = torch.ones(n, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     A = torch.from_numpy(A_np).to(dev)
     B = torch.zeros_like(A)
     Bf = torch.zeros_like(A)
@@ -368,7 +378,8 @@ def _kernel_sha():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device_common.h", "gen_dft.py"):
+    for f in ("device_common.h", "gen_dft.py", "kernels.hip", "stages.h", "xy_stages.h", "zstage_full.hip",
+              "zstage_tt3d.hip", "zstage_tt4d.hip", "zstage_tucker.hip"):
         with open(os.path.join(ROOT, "paper_2010_00520_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
