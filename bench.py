@@ -33,6 +33,7 @@ import synth  # noqa: E402
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 PEAK_FP32_VALU_TFLOPS = 157.3  # packed; non-packed issue is half of it
+PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense
 
 
 def parse():
@@ -45,6 +46,8 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run 10 plain device copies of MIB MiB (reference for HBM byte counters)")
     ap.add_argument("--fmt", default=None, help="override the compressed format")
+    ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
+                    help="override the restoration arithmetic")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -166,8 +169,7 @@ SERVING_SKIP = {
     # (grid, format) pairs left out of the stream, with the reason
     ((32, 32, 32), "tt4d"): "host TT-SVD of the 64^3 x 450 operator (Gram of a 2560-row unfolding) takes too long",
     ((24, 24, 24), "tt4d"): "host TT-SVD of the 48^3 x 450 operator takes too long",
-    ((64, 16, 16), "tucker3d"): "128-point x axis not supported by the xy-FFT stage",
-    ((64, 16, 16), "tt4d"): "128-point x axis not supported by the xy-FFT stage",
+    ((64, 16, 16), "tt4d"): "host TT-SVD of the 128 x 32 x 32 x 450 operator takes too long",
 }
 
 
@@ -276,6 +278,7 @@ def main():
 
     w = workload(args.workload)
     fmt = args.fmt or w.fmt
+    prec = args.prec or w.precision
     A_np = synth.patterns_for(w)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
@@ -292,7 +295,7 @@ def main():
     out = {}
     with P.Context(0) as ctx:
         t0 = time.perf_counter()
-        op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=w.precision)
+        op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
         setup_s = time.perf_counter() - t0
         full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
         info, finfo = op.info(), full.info()
@@ -320,7 +323,12 @@ def main():
     valu_flops = fft_flops(w.K, n, ndir, nrhs) if zname.startswith("fused") else 0.0
     mfma_tfs = flops / (zms * 1e-3) / 1e12
     hbm_gbs = alg_bytes / (zms * 1e-3) / 1e9
-    cand = [("mfma", mfma_tfs, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s"), ("hbm", hbm_gbs, PEAK_HBM_GBS, "GB/s")]
+    if prec == "bf16x3":
+        # each FP32 product is three bf16 products (hi*hi + hi*lo + lo*hi) on the bf16 matrix cores
+        cand = [("mfma", 3 * mfma_tfs, PEAK_BF16_MFMA_TFLOPS, "TFLOP/s")]
+    else:
+        cand = [("mfma", mfma_tfs, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s")]
+    cand.append(("hbm", hbm_gbs, PEAK_HBM_GBS, "GB/s"))
     if valu_flops:
         cand.append(("alu", valu_flops / (zms * 1e-3) / 1e12, PEAK_FP32_VALU_TFLOPS, "TFLOP/s"))
     bound = max(cand, key=lambda c: c[1] / c[2])
@@ -351,10 +359,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if prec == "fp32" else "bf16x3 (f32 accumulate)",
         "data": "synthetic",
         "config": {"workload": w.name, "K": list(w.K), "box": w.box, "L": w.L, "n_dir": ndir, "fmt": fmt,
-                   "tol": w.tol, "nrhs": nrhs, "precision": w.precision},
+                   "tol": w.tol, "nrhs": nrhs, "precision": prec},
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "uncompressed": {"value": value_f, "ms_per_step": ms_f, "p50_ms": float(np.percentile(lat_f, 50)),

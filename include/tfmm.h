@@ -73,8 +73,9 @@ typedef enum {
                               root r12 x r34, Eq. (11), balanced tree {1,2}{3,4}       */
 } tfmm_format;
 
-/* Arithmetic of the restoration contractions (the FFTs and the pointwise
- * product are always FP32).  BF16X3 splits each FP32 operand into a bf16 high
+/* Arithmetic of the per-direction restoration contractions (the FFTs, the
+ * pointwise product and the once-per-call contraction of a 4-D core with the
+ * direction factor are always FP32).  BF16X3 splits each FP32 operand into a bf16 high
  * part and a bf16 remainder and accumulates hi*hi + hi*lo + lo*hi in FP32 on
  * the matrix cores. */
 typedef enum { TFMM_PREC_FP32 = 0, TFMM_PREC_BF16X3 = 1 } tfmm_precision;
@@ -89,7 +90,8 @@ typedef enum { TFMM_NEAR_CHEB = 0, TFMM_NEAR_KAPPA = 1 } tfmm_near_rule;
  * nodes in cos(theta), ascending, times n_phi uniform nodes phi_j = 2 pi j /
  * n_phi; direction index p = i_theta * n_phi + j_phi. */
 typedef struct {
-  int32_t K[3];            /* box grid Kx, Ky, Kz; each one of 4, 8, 12, 16, 24, 32
+  int32_t K[3];            /* box grid Kx, Ky, Kz; each one of 4, 8, 12, 16, 24, 32,
+                              Kx also 64 or 128, with Kx * Ky <= 2048
                               (FFT grid n_i = 2 K_i)                                */
   double box_size;         /* box edge a, in the length unit of 1/k                  */
   double k;                /* real wavenumber (lossless medium)                       */

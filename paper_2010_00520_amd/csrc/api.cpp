@@ -231,10 +231,15 @@ tfmm_status roots_table(tfmm_ctx c, int n3, float2** out) {
 tfmm_status validate_grid(const int K[3]) {
   for (int i = 0; i < 3; ++i)
     if (K[i] < 1) return fail(TFMM_ERR_INVALID_ARG, "box grid dimensions must be positive");
-  for (int i = 0; i < 3; ++i)
-    if (!supported_len(2 * K[i]))
-      return fail(TFMM_ERR_UNSUPPORTED,
-                  "box grid dimension " + std::to_string(K[i]) + " unsupported (need 4, 8, 12, 16, 24 or 32)");
+  for (int i = 0; i < 3; ++i) {
+    const bool long_x = i == 0 && (K[i] == 64 || K[i] == 128);
+    if (!supported_len(2 * K[i]) && !long_x)
+      return fail(TFMM_ERR_UNSUPPORTED, "box grid dimension " + std::to_string(K[i]) +
+                                            " unsupported (need 4, 8, 12, 16, 24 or 32; Kx may also be 64 or 128)");
+  }
+  // one z-plane of the xy spectrum must fit the 64 KB LDS slab of the xy passes
+  if ((size_t)4 * K[0] * K[1] * sizeof(float2) > 65536)
+    return fail(TFMM_ERR_UNSUPPORTED, "x-y plane too large (need Kx * Ky <= 2048)");
   return TFMM_OK;
 }
 
@@ -417,7 +422,6 @@ tfmm_status check_problem(const tfmm_problem* P, int* ndir, int* L, int* nth, in
   if (s != TFMM_OK) return s;
   if ((int)P->fmt < 0 || (int)P->fmt > 5) return fail(TFMM_ERR_INVALID_ARG, "unknown format");
   if ((int)P->prec < 0 || (int)P->prec > 1) return fail(TFMM_ERR_INVALID_ARG, "unknown precision");
-  if (P->prec == TFMM_PREC_BF16X3) return fail(TFMM_ERR_UNSUPPORTED, "bf16x3 restoration is not built yet");
   int l = P->L;
   if (l <= 0) {
     if (!(P->digits > 0) || !(P->k > 0) || !(P->box_size > 0))
@@ -551,6 +555,11 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   float2* roots = nullptr;
   s = roots_table(c, n3, &roots);
   if (s != TFMM_OK) return s;
+  float2* twx = nullptr;
+  if (n1 > 64) {
+    s = roots_table(c, n1, &twx);
+    if (s != TFMM_OK) return s;
+  }
   tfmm::ZArgs z{};
   z.fmt = op->zfmt;
   z.n1 = n1; z.n2 = n2; z.n3 = n3; z.K3 = K3; z.nq = op->nq;
@@ -566,6 +575,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   z.KC = op->KC;
   z.cb = op->cb;
   z.lds_bytes = op->lds;
+  z.bf = op->prec == TFMM_PREC_BF16X3 ? 1 : 0;
   const float scale = 1.0f / (float)((double)n1 * n2 * n3);
   if (op->fused) {
     z.KC = op->fKC;
@@ -600,7 +610,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
       bool ok = false;
       {
         Launch L(c, st, "fwd_xy");
-        HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, st, &ok));
+        HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, twx, st, &ok));
         L.done();
       }
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "xy-FFT sizes unsupported");
@@ -615,7 +625,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "z-stage size unsupported");
       {
         Launch L(c, st, "inv_xy");
-        HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, scale, st, &ok));
+        HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, scale, twx, st, &ok));
         L.done();
       }
     }

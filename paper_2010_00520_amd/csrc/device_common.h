@@ -102,3 +102,98 @@ __device__ __forceinline__ void block_cgemm(float2* lds, int M, int N, int K, in
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Split-BF16 (bf16x3) arithmetic.  A complex FP32 value v is stored as two
+// dwords: hi = (bf16(v.x), bf16(v.y)) and lo = (bf16(v.x - hi.x),
+// bf16(v.y - hi.y)), round to nearest even, so an operand occupies the same
+// 8 bytes as complex64.  Products use hi*hi + hi*lo + lo*hi with FP32
+// accumulation; the dropped lo*lo term and the split itself leave a relative
+// error of a few 2^-18 per product.
+// ---------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned bf16_bits_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+__device__ __forceinline__ uint2 split_bf3(float2 v) {
+  const unsigned rh = bf16_bits_rne(v.x), ih = bf16_bits_rne(v.y);
+  const float rl = v.x - __uint_as_float(rh << 16), il = v.y - __uint_as_float(ih << 16);
+  return make_uint2(rh | (ih << 16), bf16_bits_rne(rl) | (bf16_bits_rne(il) << 16));
+}
+
+__device__ __forceinline__ v4f mfma_bf16(v4u a, v4u b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
+                                                 0, 0);
+}
+
+// Real embedding of a packed (re, im) bf16 dword for the A operand:
+// row ri = 0 takes (re, -im), row ri = 1 takes (im, re).
+__device__ __forceinline__ unsigned embed_a_bf(unsigned d, int ri) {
+  return ri == 0 ? (d ^ 0x80000000u) : ((d >> 16) | (d << 16));
+}
+
+// acc += A' B' for one 16x16x32 bf16 K-step in split arithmetic.
+__device__ __forceinline__ v4f mfma_bf3(v4u ahi, v4u alo, v4u bhi, v4u blo, v4f acc) {
+  acc = mfma_bf16(ahi, bhi, acc);
+  acc = mfma_bf16(ahi, blo, acc);
+  acc = mfma_bf16(alo, bhi, acc);
+  return acc;
+}
+
+// Block-cooperative batched complex GEMM, split-BF16 operands and result in
+// LDS (uint2 per complex, see split_bf3).  Same tiling as block_cgemm: a wave
+// computes an 8-row x 32-column block; one 16x16x32 bf16 step consumes 16
+// complex k (lane group kg = l/16 supplies k0 + 4kg .. k0 + 4kg + 3).
+template <int NW>
+__device__ __forceinline__ void block_cgemm_bf3(uint2* lds, int M, int N, int K, int nb, LOp A, LOp B, LOp C) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int tmN = (M + 7) >> 3, tpN = (N + 31) >> 5;
+  const int per = tmN * tpN, ntiles = nb * per;
+  const int ks = (K + 15) >> 4;
+  const int kg = l >> 4, ri = l & 1;
+  for (int tile = w; tile < ntiles; tile += NW) {
+    const int bat = tile / per, rem = tile - bat * per;
+    const int tm = rem / tpN, tp = rem - tm * tpN;
+    const int am = tm * 8 + ((l & 15) >> 1);
+    const int bn0 = tp * 32 + (l & 15), bn1 = bn0 + 16;
+    const bool aok = am < M, b0ok = bn0 < N, b1ok = bn1 < N;
+    const uint2* ap = lds + A.off + (aok ? am : 0) * A.s0 + bat * A.sb;
+    const uint2* bp0 = lds + B.off + (b0ok ? bn0 : 0) * B.s1 + bat * B.sb;
+    const uint2* bp1 = lds + B.off + (b1ok ? bn1 : 0) * B.s1 + bat * B.sb;
+    v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < ks; ++s) {
+      v4u ahi, alo, b0hi, b0lo, b1hi, b1lo;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int k = 16 * s + 4 * kg + d;
+        const bool kok = k < K;
+        const uint2 va = (aok && kok) ? ap[k * A.s1] : make_uint2(0u, 0u);
+        const uint2 vb0 = (b0ok && kok) ? bp0[k * B.s0] : make_uint2(0u, 0u);
+        const uint2 vb1 = (b1ok && kok) ? bp1[k * B.s0] : make_uint2(0u, 0u);
+        ahi[d] = embed_a_bf(va.x, ri);
+        alo[d] = embed_a_bf(va.y, ri);
+        b0hi[d] = vb0.x;
+        b0lo[d] = vb0.y;
+        b1hi[d] = vb1.x;
+        b1lo[d] = vb1.y;
+      }
+      acc0 = mfma_bf3(ahi, alo, b0hi, b0lo, acc0);
+      acc1 = mfma_bf3(ahi, alo, b1hi, b1lo, acc1);
+    }
+    const int cm0 = tm * 8 + 2 * (l >> 4);
+    uint2* cb = lds + C.off + bat * C.sb;
+    if (b0ok) {
+      if (cm0 < M) cb[cm0 * C.s0 + bn0 * C.s1] = split_bf3(make_float2(acc0[0], acc0[1]));
+      if (cm0 + 1 < M) cb[(cm0 + 1) * C.s0 + bn0 * C.s1] = split_bf3(make_float2(acc0[2], acc0[3]));
+    }
+    if (b1ok) {
+      if (cm0 < M) cb[cm0 * C.s0 + bn1 * C.s1] = split_bf3(make_float2(acc1[0], acc1[1]));
+      if (cm0 + 1 < M) cb[(cm0 + 1) * C.s0 + bn1 * C.s1] = split_bf3(make_float2(acc1[2], acc1[3]));
+    }
+  }
+}

@@ -25,7 +25,7 @@ import sys
 import numpy as np
 
 LINE_SIZES = (2, 4, 6, 8, 12, 16, 24, 32, 48, 64)
-SMALL_SIZES = (1, 2, 3, 4, 5, 6, 7, 8)
+SMALL_SIZES = (1, 2, 3, 4, 5, 6, 7, 8, 16)
 
 
 def f32hex(v: float) -> str:

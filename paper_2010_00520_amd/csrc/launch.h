@@ -27,6 +27,7 @@ struct ZArgs {
   int KC;                     // complex contraction chunk
   int cb;                     // column blocks per wave (pencil tile = 64*cb)
   int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
+  int bf;                     // 1: split-BF16 (bf16x3) restoration, 0: FP32
 };
 
 // LDS bytes a restoration of a qt-pencil tile needs for a format / ranks /
@@ -41,10 +42,12 @@ struct RhsPtrs {
   float2* b[TFMM_MAX_RHS_PER_LAUNCH];
 };
 
+// xy passes of the three-pass pipeline.  n1 in {8,...,64, 128, 256}, n2 <= 64;
+// twx = exp(-2 pi i m / n1), m < n1, is read only when n1 > 64.
 hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         hipStream_t st, bool* supported);
+                         const float2* twx, hipStream_t st, bool* supported);
 hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         float scale, hipStream_t st, bool* supported);
+                         float scale, const float2* twx, hipStream_t st, bool* supported);
 hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported);
 
 // Fused single-kernel translation (one block per direction) for cubic grids

@@ -48,6 +48,70 @@ __device__ __forceinline__ void restore_final_chunk(v4f (&acc)[T][CB], const flo
   }
 }
 
+// Split-BF16 variant of restore_final_chunk: one 16x16x32 bf16 step covers 16
+// complex k (lane group kg supplies k = 16s + 4kg .. +3), three MFMAs per step.
+template <int T, int CB>
+__device__ __forceinline__ void restore_final_chunk_bf3(v4f (&acc)[T][CB], const uint2* sV, const uint2* sW, int KC,
+                                                        int kc) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15;
+  const int kg = l >> 4, ri = l & 1;
+  const int ks = (kc + 15) >> 4;
+  for (int s = 0; s < ks; ++s) {
+    v4u ahi[T], alo[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int fz = 8 * t + (j >> 1);
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int k = 16 * s + 4 * kg + d;
+        const uint2 v = k < kc ? sV[fz * KC + k] : make_uint2(0u, 0u);
+        ahi[t][d] = embed_a_bf(v.x, ri);
+        alo[t][d] = embed_a_bf(v.y, ri);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int ql = (w * CB + c) * 16 + j;
+      v4u bhi, blo;
+#pragma unroll
+      for (int d = 0; d < 4; ++d) {
+        const int k = 16 * s + 4 * kg + d;
+        const uint2 v = k < kc ? sW[ql * KC + k] : make_uint2(0u, 0u);
+        bhi[d] = v.x;
+        blo[d] = v.y;
+      }
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t][c] = mfma_bf3(ahi[t], alo[t], bhi, blo, acc[t][c]);
+    }
+  }
+}
+
+// Store of a staged operand value: complex64 as is, or split into bf16 hi/lo.
+template <bool BF>
+__device__ __forceinline__ void stage(float2* lds, int i, float2 v) {
+  if constexpr (BF)
+    reinterpret_cast<uint2*>(lds)[i] = split_bf3(v);
+  else
+    lds[i] = v;
+}
+
+template <bool BF, int NW>
+__device__ __forceinline__ void stage_gemm(float2* lds, int M, int N, int K, int nb, LOp A, LOp B, LOp C) {
+  if constexpr (BF)
+    block_cgemm_bf3<NW>(reinterpret_cast<uint2*>(lds), M, N, K, nb, A, B, C);
+  else
+    block_cgemm<NW>(lds, M, N, K, nb, A, B, C);
+}
+
+template <bool BF, int T, int CB>
+__device__ __forceinline__ void stage_final(v4f (&acc)[T][CB], float2* sV, float2* sW, int KC, int kc) {
+  if constexpr (BF)
+    restore_final_chunk_bf3<T, CB>(acc, reinterpret_cast<const uint2*>(sV), reinterpret_cast<const uint2*>(sW), KC,
+                                   kc);
+  else
+    restore_final_chunk<T, CB>(acc, sV, sW, KC, kc);
+}
+
 // A chunk of a factor copied to LDS: element e (row e >> kcs, column e & (KC-1))
 // is base[row*rstride + c0 + col] for col < kc and row < rows, else zero.
 struct ChunkSrc {
@@ -76,17 +140,18 @@ struct ChunkPrefetch {
       ry[i] = v.y;
     }
   }
+  template <bool BF>
   __device__ __forceinline__ void store(float2* dst, const ChunkSrc& src, int count, int c0, int kc) {
 #pragma unroll
     for (int i = 0; i < PF; ++i) {
       const int e = threadIdx.x + i * NT;
-      if (e < count) dst[e] = make_float2(rx[i], ry[i]);
+      if (e < count) stage<BF>(dst, e, make_float2(rx[i], ry[i]));
     }
-    for (int e = threadIdx.x + PF * NT; e < count; e += NT) dst[e] = src.at(e, c0, kc);
+    for (int e = threadIdx.x + PF * NT; e < count; e += NT) stage<BF>(dst, e, src.at(e, c0, kc));
   }
 };
 
-template <int FMT, int T, int CB, int NW>
+template <int FMT, int T, int CB, int NW, bool BF>
 __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, int p, int q0, float2* lds) {
   constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
@@ -119,8 +184,8 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       const int nfx = QT / n2, fx0 = q0 / n2;
       const int oU1 = 0, oU2 = oU1 + nfx * r1, oC = oU2 + n2 * r2, oW1 = oC + r1 * r2 * KC,
                 oW = oW1 + nfx * r2 * KC, oV = oW + QT * KC;
-      for (int e = tid; e < nfx * r1; e += NT) lds[oU1 + e] = U1[fx0 * r1 + e];
-      for (int e = tid; e < n2 * r2; e += NT) lds[oU2 + e] = U2[e];
+      for (int e = tid; e < nfx * r1; e += NT) stage<BF>(lds, oU1 + e, U1[fx0 * r1 + e]);
+      for (int e = tid; e < n2 * r2; e += NT) stage<BF>(lds, oU2 + e, U2[e]);
       // core chunk element e = (a*r2 + b)*KC + cl  <-  C[a][b][c0 + cl]
       const int csz = r1 * r2 * KC;
       const ChunkSrc src{C, r3, r1 * r2, kcs, KC};
@@ -128,23 +193,23 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       pf.load(src, csz, 0, min(KC, r3));
       for (int c0 = 0; c0 < r3; c0 += KC) {
         const int kc = min(KC, r3 - c0);
-        pf.store(lds + oC, src, csz, c0, kc);
+        pf.template store<BF>(lds + oC, src, csz, c0, kc);
         for (int e = tid; e < N3 * KC; e += NT) {
           const int cl = e & (KC - 1), fz = e >> kcs;
-          lds[oV + e] = cl < kc ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f);
+          stage<BF>(lds, oV + e, cl < kc ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f));
         }
         __syncthreads();
         if (c0 + KC < r3) pf.load(src, csz, c0 + KC, min(KC, r3 - c0 - KC));
         // W1[fx][(b,cl)] = sum_a U1[fx][a] C[a][(b,cl)]             (Fig. 3(a) step 1)
-        block_cgemm<NW>(lds, nfx, r2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, r2 * KC, 1, 0},
-                        LOp{oW1, r2 * KC, 1, 0});
+        stage_gemm<BF, NW>(lds, nfx, r2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, r2 * KC, 1, 0},
+                           LOp{oW1, r2 * KC, 1, 0});
         __syncthreads();
         // W[(fx,fy)][cl] = sum_b W1[fx][b][cl] U2[fy][b]              (step 2), batch over cl
-        block_cgemm<NW>(lds, nfx, n2, r2, kc, LOp{oW1, r2 * KC, KC, 1}, LOp{oU2, 1, r2, 0},
-                        LOp{oW, n2 * KC, KC, 1});
+        stage_gemm<BF, NW>(lds, nfx, n2, r2, kc, LOp{oW1, r2 * KC, KC, 1}, LOp{oU2, 1, r2, 0},
+                           LOp{oW, n2 * KC, KC, 1});
         __syncthreads();
         // T~[fz][q] += sum_c U3[fz][c] W[q][c]                         (step 3)
-        restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);
+        stage_final<BF, T, CB>(acc, lds + oV, lds + oW, KC, kc);
         __syncthreads();
       }
     } else if constexpr (FMT == ZF_TT3D) {
@@ -154,7 +219,7 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       const float2* U3 = a.fbase + d[3];
       const int nfx = QT / n2, fx0 = q0 / n2;
       const int oU1 = 0, oC = oU1 + nfx * r1, oW = oC + r1 * n2 * KC, oV = oW + QT * KC;
-      for (int e = tid; e < nfx * r1; e += NT) lds[oU1 + e] = U1[fx0 * r1 + e];
+      for (int e = tid; e < nfx * r1; e += NT) stage<BF>(lds, oU1 + e, U1[fx0 * r1 + e]);
       // core chunk element e = (a*n2 + y)*KC + bl  <-  C[a][y][b0 + bl]
       const int csz = r1 * n2 * KC;
       const ChunkSrc src{C, r2, r1 * n2, kcs, KC};
@@ -162,18 +227,18 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       pf.load(src, csz, 0, min(KC, r2));
       for (int b0 = 0; b0 < r2; b0 += KC) {
         const int kc = min(KC, r2 - b0);
-        pf.store(lds + oC, src, csz, b0, kc);
+        pf.template store<BF>(lds + oC, src, csz, b0, kc);
         for (int e = tid; e < N3 * KC; e += NT) {
           const int bl = e & (KC - 1), fz = e >> kcs;
-          lds[oV + e] = bl < kc ? U3[fz * r2 + b0 + bl] : make_float2(0.f, 0.f);
+          stage<BF>(lds, oV + e, bl < kc ? U3[fz * r2 + b0 + bl] : make_float2(0.f, 0.f));
         }
         __syncthreads();
         if (b0 + KC < r2) pf.load(src, csz, b0 + KC, min(KC, r2 - b0 - KC));
         // W[(fx,fy)][bl] = sum_a U1[fx][a] C[a][(fy,bl)]              (Fig. 4(a) step 1)
-        block_cgemm<NW>(lds, nfx, n2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, n2 * KC, 1, 0},
-                        LOp{oW, n2 * KC, 1, 0});
+        stage_gemm<BF, NW>(lds, nfx, n2 * KC, r1, 1, LOp{oU1, r1, 1, 0}, LOp{oC, n2 * KC, 1, 0},
+                           LOp{oW, n2 * KC, 1, 0});
         __syncthreads();
-        restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);  // step 2
+        stage_final<BF, T, CB>(acc, lds + oV, lds + oW, KC, kc);  // step 2
         __syncthreads();
       }
     } else {  // ZF_TT4D: W = T1 (direction-independent), V = S_p (Fig. 4(b))
@@ -187,14 +252,14 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       pf.load(src, wsz, 0, min(KC, r2));
       for (int b0 = 0; b0 < r2; b0 += KC) {
         const int kc = min(KC, r2 - b0);
-        pf.store(lds + oW, src, wsz, b0, kc);
+        pf.template store<BF>(lds + oW, src, wsz, b0, kc);
         for (int e = tid; e < N3 * KC; e += NT) {
           const int bl = e & (KC - 1), fz = e >> kcs;
-          lds[oV + e] = bl < kc ? V[fz * r2 + b0 + bl] : make_float2(0.f, 0.f);
+          stage<BF>(lds, oV + e, bl < kc ? V[fz * r2 + b0 + bl] : make_float2(0.f, 0.f));
         }
         __syncthreads();
         if (b0 + KC < r2) pf.load(src, wsz, b0 + KC, min(KC, r2 - b0 - KC));
-        restore_final_chunk<T, CB>(acc, lds + oV, lds + oW, KC, kc);
+        stage_final<BF, T, CB>(acc, lds + oV, lds + oW, KC, kc);
         __syncthreads();
       }
     }
@@ -303,7 +368,7 @@ __device__ __forceinline__ void zfft_rhs(const v4f (&acc)[T][CB], float2* H, lon
 // Pass 2 of the three-pass pipeline: one block per (pencil tile, direction);
 // the restored tile is shared by every RHS of the launch.
 // ---------------------------------------------------------------------------
-template <int FMT, int T, int CB>
+template <int FMT, int T, int CB, bool BF>
 __global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
   extern __shared__ float2 lds[];
   constexpr int NW = 4, QT = 16 * CB * NW;
@@ -311,7 +376,7 @@ __global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
   const int q0 = blockIdx.x * QT;
   const int pl = blockIdx.y, p = a.p0 + pl;
   v4f acc[T][CB];
-  restore_tile<FMT, T, CB, NW>(acc, a, p, q0, lds);
+  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
   ZTwiddles<T> Z;
   Z.load(a.roots);
   for (int s = 0; s < a.nrhs; ++s) {
@@ -326,7 +391,7 @@ __global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
 // runs the xy-FFTs, the z-stage and the inverse xy-FFTs on chip.  A and B are
 // the only device-memory traffic besides the stored operator.
 // ---------------------------------------------------------------------------
-template <int FMT, int N, int NW, int CB>
+template <int FMT, int N, int NW, int CB, bool BF>
 __global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float scale) {
   extern __shared__ float2 lds[];
   constexpr int T = N / 8, K = N / 2, NQ = N * N, NT = 64 * NW;
@@ -335,17 +400,17 @@ __global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float sca
   const int w = threadIdx.x >> 6;
   const int p = a.p0 + blockIdx.x;
   v4f acc[T][CB];
-  restore_tile<FMT, T, CB, NW>(acc, a, p, 0, lds);
+  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, 0, lds);
   ZTwiddles<T> Z;
   Z.load(a.roots);
   __syncthreads();
   const long long blk = (long long)K * K * K;
   for (int s = 0; s < a.nrhs; ++s) {
-    xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0);
+    xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0, nullptr);
     __syncthreads();
     zfft_rhs<T, CB>(acc, lds, 1, ZP, w * CB * 16, NQ, Z);
     __syncthreads();
-    xy_inverse<N, N, NT>(lds, P.b[s] + (long long)p * blk, K, K, ZP, 0, scale);
+    xy_inverse<N, N, NT>(lds, P.b[s] + (long long)p * blk, K, K, ZP, 0, scale, nullptr);
     __syncthreads();
   }
 }
@@ -357,30 +422,46 @@ template <> struct FusedShape<16> { static constexpr int NW = 8, CB = 2; };
 template <> struct FusedShape<24> { static constexpr int NW = 6, CB = 6; };
 template <> struct FusedShape<32> { static constexpr int NW = 8, CB = 8; };
 
-template <int FMT, int T, int CB>
-hipError_t run_zstage(const ZArgs& a, hipStream_t st) {
+template <int FMT, int T, int CB, bool BF>
+hipError_t run_zstage_p(const ZArgs& a, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_zstage<FMT, T, CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    (void)hipFuncSetAttribute((const void*)k_zstage<FMT, T, CB, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     attr = true;
   }
   dim3 grid(a.nq / (64 * CB), a.ndl);
-  hipLaunchKernelGGL((k_zstage<FMT, T, CB>), grid, dim3(256), (size_t)a.lds_bytes, st, a);
+  hipLaunchKernelGGL((k_zstage<FMT, T, CB, BF>), grid, dim3(256), (size_t)a.lds_bytes, st, a);
+  return hipGetLastError();
+}
+
+// FULL has no restoration arithmetic, so it has no split-BF16 variant.
+template <int FMT, int T, int CB>
+hipError_t run_zstage(const ZArgs& a, hipStream_t st) {
+  if constexpr (FMT != ZF_FULL)
+    if (a.bf) return run_zstage_p<FMT, T, CB, true>(a, st);
+  return run_zstage_p<FMT, T, CB, false>(a, st);
+}
+
+template <int FMT, int N, bool BF>
+hipError_t run_fused_p(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_t st) {
+  constexpr int NW = FusedShape<N>::NW, CB = FusedShape<N>::CB;
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_fused<FMT, N, NW, CB, BF>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB, BF>), dim3(a.ndl), dim3(64 * NW), (size_t)a.lds_bytes, st, a, P,
+                     scale);
   return hipGetLastError();
 }
 
 template <int FMT, int N>
 hipError_t run_fused(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_t st) {
-  constexpr int NW = FusedShape<N>::NW, CB = FusedShape<N>::CB;
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void*)k_fused<FMT, N, NW, CB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    attr = true;
-  }
-  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB>), dim3(a.ndl), dim3(64 * NW), (size_t)a.lds_bytes, st, a, P, scale);
-  return hipGetLastError();
+  if constexpr (FMT != ZF_FULL)
+    if (a.bf) return run_fused_p<FMT, N, true>(a, P, scale, st);
+  return run_fused_p<FMT, N, false>(a, P, scale, st);
 }
 
 template <int FMT>

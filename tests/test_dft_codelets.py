@@ -45,7 +45,7 @@ int main() {
     if (!ok) {
       switch (n) {
 #define SCASE(N) case N: if (kind[1]=='F') dft_full_fwd_##N(x, y); else dft_full_inv_##N(x, y); break;
-        SCASE(1) SCASE(2) SCASE(3) SCASE(4) SCASE(5) SCASE(6) SCASE(7) SCASE(8)
+        SCASE(1) SCASE(2) SCASE(3) SCASE(4) SCASE(5) SCASE(6) SCASE(7) SCASE(8) SCASE(16)
       }
       nout = n;
     }
@@ -90,7 +90,7 @@ def test_pruned_codelets_match_numpy(codelet_exe, n):
     assert np.linalg.norm(yi - refi) / np.linalg.norm(refi) < 2e-7
 
 
-@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8, 16])
 def test_full_codelets_match_numpy(codelet_exe, t):
     rng = np.random.default_rng(100 + t)
     x = (rng.standard_normal(t) + 1j * rng.standard_normal(t)).astype(np.complex64)

@@ -11,6 +11,7 @@ Two kinds of checks:
   operator) within 10*gamma + 1e-6.
 """
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -24,6 +25,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 ARITH_TOL = 2e-5
+
+
+def seed_of(*parts):
+    """Deterministic seed (str hashes are salted per process)."""
+    return zlib.crc32(repr(parts).encode())
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +71,7 @@ def test_import_arithmetic_parity(ctx, fmt, K):
     n = tuple(2 * k for k in K)
     L = 3
     ndir = (L + 1) * 2 * (L + 1)
-    rng = np.random.default_rng(abs(hash((fmt, K))) % (2 ** 32))
+    rng = np.random.default_rng(seed_of(fmt, K))
     ranks = {"tucker4d": (5, 6, 3, 7), "tt4d": (5, 9, 7), "htucker4d": (4, 5, 3, 6, 9, 8)}.get(fmt)
     rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
     op = ctx.import_factors(K, L, fmt, rk, data)
@@ -173,3 +179,88 @@ def test_three_pass_and_fused_agree(fmt):
     for got in outs:
         assert O.rel_l2(got, ref) < ARITH_TOL
     assert O.rel_l2(outs[0], outs[1]) < ARITH_TOL
+
+
+# Split-BF16 restoration: each FP32 operand x = hi + lo + r with hi = bf16(x),
+# lo = bf16(x - hi) (both round to nearest), so |r| <= 2^-18 |x|; the dropped
+# lo*lo term is <= 2^-18 |x y| as well, so a product carries <= ~3 * 2^-18 =
+# 1.1e-5 relative error.  Three chained contractions (Fig. 3a / Fig. 4) then
+# stay below ~3.5e-5 of the restored operator, to which the FP32 FFTs add
+# ~1e-6; 1e-4 leaves a margin for the norm of sums of random terms.
+BF_TOL = 1e-4
+
+
+@pytest.mark.parametrize("K", [(8, 8, 8), (8, 12, 4)])
+@pytest.mark.parametrize("fmt", ["tucker3d", "tt3d", "tucker4d", "tt4d", "htucker4d"])
+def test_import_bf16x3_parity(ctx, fmt, K):
+    n = tuple(2 * k for k in K)
+    L = 3
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(seed_of("bf", fmt, K))
+    ranks = {"tucker4d": (5, 6, 3, 7), "tt4d": (5, 9, 7), "htucker4d": (4, 5, 3, 6, 9, 8)}.get(fmt)
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    op = ctx.import_factors(K, L, fmt, rk, data, prec="bf16x3")
+    assert op.info()["prec"] == 1
+    A = synth.gaussian_patterns((2, ndir) + tuple(K), 8)
+    ref = O.translate_compressed(A, comp)
+    got = gpu_translate(ctx, op, A)
+    err = O.rel_l2(got, ref)
+    assert err < BF_TOL, (fmt, K, err)
+    # the split arithmetic must actually be more accurate than plain bf16 (~4e-3)
+    for s in range(2):
+        for p in (0, ndir - 1):
+            assert O.rel_l2(got[s, p], ref[s, p]) < 5 * BF_TOL
+    op.release()
+
+
+def test_plain_16cubed_tucker3d_bf16x3_end_to_end(ctx):
+    w = synth.PLAIN
+    op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="tucker3d", tol=w.tol, prec="bf16x3")
+    A = synth.patterns_for(w)
+    _, _, _, Th = O.build_operator(w.K, w.box, w.k, w.L)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, O.translate_fft(A, Th)) <= 10 * w.tol + 1e-6
+    op.release()
+
+
+# x axes of 64 and 128 boxes (FFT lengths 128 and 256, split 16 x NB in LDS)
+@pytest.mark.parametrize("K", [(64, 4, 8), (128, 8, 8), (64, 32, 4)])
+@pytest.mark.parametrize("fmt", ["full", "tucker3d", "tt3d", "tt4d", "htucker4d"])
+def test_long_x_import_parity(ctx, fmt, K):
+    n = tuple(2 * k for k in K)
+    L = 3
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(seed_of("lx", fmt, K))
+    ranks = {"tt4d": (6, 10, 7), "htucker4d": (6, 5, 4, 7, 12, 9)}.get(fmt)
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    op = ctx.import_factors(K, L, fmt, rk, data)
+    A = synth.gaussian_patterns((2, ndir) + tuple(K), 9)
+    ref = O.translate_compressed(A, comp)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, ref) < ARITH_TOL, (fmt, K)
+    for s in range(2):
+        for p in (0, ndir // 3, ndir - 1):
+            assert O.rel_l2(got[s, p], ref[s, p]) < 5 * ARITH_TOL
+    op.release()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_long_x_setup_end_to_end(ctx, prec):
+    """An elongated 64 x 4 x 4 box grid, sampled and compressed by the library,
+    against the exact FP64 FFT-form translation."""
+    K, box, L, gamma = (64, 4, 4), 0.5, 5, 1e-4
+    op = ctx.setup(K=K, box=box, k=2 * math.pi, L=L, fmt="tt3d", tol=gamma, prec=prec)
+    _, _, _, Th = O.build_operator(K, box, 2 * math.pi, L)
+    A = synth.gaussian_patterns((1, Th.shape[0]) + K, 10)
+    got = gpu_translate(ctx, op, A)
+    assert O.rel_l2(got, O.translate_fft(A, Th)) <= 10 * gamma + 1e-6
+    op.release()
+
+
+def test_unsupported_grids_rejected(ctx):
+    import paper_2010_00520_amd as P
+
+    for K in [(64, 64, 4), (256, 4, 4), (4, 64, 4), (6, 4, 4)]:
+        with pytest.raises(P.TfmmError) as e:
+            ctx.setup(K=K, box=0.5, L=3, fmt="full")
+        assert e.value.status == 2, K
