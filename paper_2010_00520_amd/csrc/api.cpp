@@ -80,6 +80,8 @@ struct tfmm_op_s {
   int zfmt = 0, cb = 1, KC = 8, lds = 0;
   bool fused = false;
   int fKC = 8, flds = 0;
+  // Tucker family: register-chained restoration (3-pass tile / fused tile)
+  bool tk2 = false, ftk2 = false;
   size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
   tfmm_op_info info{};
   std::atomic<int> refs{0};
@@ -110,6 +112,7 @@ struct KernelStat {
 struct tfmm_ctx_s {
   int device = 0;
   bool no_fused = false;               // TFMM_NO_FUSED=1: always use the three-pass pipeline
+  bool no_tk2 = false;                 // TFMM_NO_TK2=1: Tucker restoration through LDS-staged products
   size_t budget = 0, used = 0;
   std::recursive_mutex mu;
   // translation scratch, one per stream slot (slot 0 = tfmm_translate; 1..S = scheduler streams)
@@ -273,11 +276,20 @@ tfmm_status plan_zstage(tfmm_op op) {
       r2 = std::max(r2, op->desc[8 * p + 5]);
     }
   const size_t lds_max = 160 * 1024;
+  const bool bf = op->prec == TFMM_PREC_BF16X3;
+  op->tk2 = op->ftk2 = false;
   if (op->zfmt != tfmm::ZF_FULL) {
     const size_t cap = 96 * 1024;
     int KC = 16;
     while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2) > cap) KC /= 2;
     size_t need = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2);
+    if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2) {
+      const size_t need2 = tfmm::tucker2_lds_bytes(n2, n3, 64 * op->cb, r1, r2, bf);
+      if (need2 <= lds_max) {
+        op->tk2 = true;
+        need = need2;
+      }
+    }
     if (need > lds_max) return fail(TFMM_ERR_UNSUPPORTED, "ranks too large for the LDS-resident restoration");
     op->KC = KC;
     op->lds = (int)need;
@@ -289,12 +301,21 @@ tfmm_status plan_zstage(tfmm_op op) {
     const size_t hbytes = (size_t)n1 * n2 * zp * sizeof(float2);
     int KC = 16;
     size_t rb = 0;
+    bool ftk2 = false;
     if (op->zfmt != tfmm::ZF_FULL) {
       while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2) > lds_max) KC /= 2;
       rb = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2);
+      if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2) {
+        const size_t rb2 = tfmm::tucker2_lds_bytes(n2, n3, n1 * n2, r1, r2, bf);
+        if (rb2 <= lds_max) {
+          ftk2 = true;
+          rb = rb2;
+        }
+      }
     }
     if (hbytes <= lds_max && rb <= lds_max) {
       op->fused = true;
+      op->ftk2 = ftk2;
       op->fKC = KC;
       op->flds = (int)std::max(hbytes, rb);
     }
@@ -576,10 +597,12 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   z.cb = op->cb;
   z.lds_bytes = op->lds;
   z.bf = op->prec == TFMM_PREC_BF16X3 ? 1 : 0;
+  z.tk2 = op->tk2 ? 1 : 0;
   const float scale = 1.0f / (float)((double)n1 * n2 * n3);
   if (op->fused) {
     z.KC = op->fKC;
     z.lds_bytes = op->flds;
+    z.tk2 = op->ftk2 ? 1 : 0;
     z.p0 = 0;
     z.ndl = nd;
     for (int r0 = 0; r0 < nr_total; r0 += rhs_group) {
@@ -784,6 +807,8 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
   const char* nf = std::getenv("TFMM_NO_FUSED");
   c->no_fused = nf && nf[0] == '1';
+  const char* nt = std::getenv("TFMM_NO_TK2");
+  c->no_tk2 = nt && nt[0] == '1';
   for (int i = 0; i < 2; ++i)
     if (hipStreamCreateWithFlags(&c->streams[i], hipStreamNonBlocking) != hipSuccess) {
       delete c;

@@ -126,6 +126,15 @@ __device__ __forceinline__ uint2 split_bf3(float2 v) {
   return make_uint2(rh | (ih << 16), bf16_bits_rne(rl) | (bf16_bits_rne(il) << 16));
 }
 
+// Store of a staged operand value: complex64 as is, or split into bf16 hi/lo.
+template <bool BF>
+__device__ __forceinline__ void stage(float2* lds, int i, float2 v) {
+  if constexpr (BF)
+    reinterpret_cast<uint2*>(lds)[i] = split_bf3(v);
+  else
+    lds[i] = v;
+}
+
 __device__ __forceinline__ v4f mfma_bf16(v4u a, v4u b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0,
                                                  0, 0);

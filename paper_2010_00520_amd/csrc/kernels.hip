@@ -12,6 +12,7 @@
 
 #include "device_common.h"
 #include "launch.h"
+#include "tucker_restore.h"
 #include "xy_stages.h"
 
 namespace tfmm {
@@ -264,6 +265,15 @@ size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1,
     e = (size_t)qt * KC + (size_t)n3 * KC;
   (void)n1;
   return e * sizeof(float2);
+}
+
+size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf) {
+  TuckerLds L;
+  if (bf)
+    L.plan<true>(qt / n2, n2, n3, r1, r2);
+  else
+    L.plan<false>(qt / n2, n2, n3, r1, r2);
+  return (size_t)L.total * sizeof(float2);
 }
 
 // ---------------------------------------------------------------------------

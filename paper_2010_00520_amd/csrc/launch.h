@@ -28,11 +28,14 @@ struct ZArgs {
   int cb;                     // column blocks per wave (pencil tile = 64*cb)
   int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
   int bf;                     // 1: split-BF16 (bf16x3) restoration, 0: FP32
+  int tk2;                    // Tucker: 1 = register-chained restoration (tucker_restore.h)
 };
 
 // LDS bytes a restoration of a qt-pencil tile needs for a format / ranks /
 // chunk (host-side planning; qt = n1*n2 for the fused kernel).
 size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1, int r2);
+// LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
+size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf);
 
 // Per-RHS base pointers of one launch: rhs s reads A_s[n_dir][Kx][Ky][Kz] and
 // writes B_s of the same shape (complex64).  Passed by value.

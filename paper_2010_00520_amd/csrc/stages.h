@@ -6,6 +6,7 @@
 
 #include "device_common.h"
 #include "launch.h"
+#include "tucker_restore.h"
 #include "xy_stages.h"
 
 namespace tfmm {
@@ -84,15 +85,6 @@ __device__ __forceinline__ void restore_final_chunk_bf3(v4f (&acc)[T][CB], const
       for (int t = 0; t < T; ++t) acc[t][c] = mfma_bf3(ahi[t], alo[t], bhi, blo, acc[t][c]);
     }
   }
-}
-
-// Store of a staged operand value: complex64 as is, or split into bf16 hi/lo.
-template <bool BF>
-__device__ __forceinline__ void stage(float2* lds, int i, float2 v) {
-  if constexpr (BF)
-    reinterpret_cast<uint2*>(lds)[i] = split_bf3(v);
-  else
-    lds[i] = v;
 }
 
 template <bool BF, int NW>
@@ -176,6 +168,10 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
     const int* d = a.desc + 8 * p;
     const int KC = a.KC, kcs = 31 - __builtin_clz(KC);  // KC is a power of two
     if constexpr (FMT == ZF_TUCKER) {
+      if (a.tk2) {
+        restore_tucker<T, CB, NW, BF>(acc, a, d, q0, lds);
+        return;
+      }
       const int r1 = d[4], r2 = d[5], r3 = d[6];
       const float2* C = a.cbase + d[0];
       const float2* U1 = a.fbase + d[1];

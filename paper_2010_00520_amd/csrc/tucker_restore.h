@@ -1,0 +1,400 @@
+// Tucker-3D restoration of an operator tile straight into the z-stage
+// accumulators (Fig. 3(a): x-mode, then y-mode, then z-mode products), with
+// the y-mode product kept in registers:
+//
+//   W1[fx][c][b]   = sum_a U1[fx][a] C[a][b][c]          block-wide, via LDS
+//   W[q][c]        = sum_b W1[fx(q)][c][b] U2[fy(q)][b]   per wave, in registers
+//   T~[fz][q]     += sum_c U3[fz][c] W[q][c]              per wave, accumulators
+//
+// processed in chunks of 8 core columns c.  The second product's MFMA output
+// tile (rows (c, re/im), columns = the wave's 16 pencils) already has the
+// register layout of the third product's B operand, so W never touches LDS
+// and each chunk needs only two block barriers.
+//
+// All operands sit in LDS "k-contiguous" (each row of a complex matrix holds
+// consecutive values of the contraction index), zero-padded to whole K-steps,
+// so fragment loads are unconditional.  Two arithmetics share the code:
+//   FP32 : 16x16x4 f32 MFMA; a K-step is 2 complex k, lane group kg supplies
+//          complex k0 + kg/2, component kg%2.
+//   BF16X3: 16x16x32 bf16 MFMA on split operands (hi*hi + hi*lo + lo*hi); a
+//          K-step is 16 complex k, lane group kg supplies complex k0+4kg..+3.
+//          The third product has only 8 complex k (16 real) per chunk, so its
+//          K-step instead concatenates hi and lo parts along k:
+//          [A_hi, A_lo] . [W_hi; W_hi] + [A_hi, A_lo] . [W_lo; 0], two MFMAs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+#include "launch.h"
+
+namespace tfmm {
+
+template <bool BF>
+struct Cx;
+
+template <>
+struct Cx<false> {
+  static constexpr int KS = 2;  // complex k per K-step
+  typedef float A;
+  typedef float B;
+  // p: the k-contiguous row at the step's first k.  A is real-embedded (row ri).
+  static __device__ __forceinline__ A load_a(const float2* p, int kg, int ri) {
+    return embed_a(p[kg >> 1], ri, kg & 1);
+  }
+  static __device__ __forceinline__ B load_b(const float2* p, int kg) {
+    const float2 v = p[kg >> 1];
+    return (kg & 1) ? v.y : v.x;
+  }
+  static __device__ __forceinline__ B zero_b() { return 0.f; }
+  static __device__ __forceinline__ v4f mma(A a, B b, v4f c) { return mfma4(a, b, c); }
+};
+
+struct BfFrag {
+  v4u hi, lo;
+};
+
+template <>
+struct Cx<true> {
+  static constexpr int KS = 16;
+  typedef BfFrag A;
+  typedef BfFrag B;
+  static __device__ __forceinline__ A load_a(const float2* p, int kg, int ri) {
+    const uint4* q = reinterpret_cast<const uint4*>(p + 4 * kg);
+    const uint4 x = q[0], y = q[1];
+    A r;
+    r.hi = v4u{embed_a_bf(x.x, ri), embed_a_bf(x.z, ri), embed_a_bf(y.x, ri), embed_a_bf(y.z, ri)};
+    r.lo = v4u{embed_a_bf(x.y, ri), embed_a_bf(x.w, ri), embed_a_bf(y.y, ri), embed_a_bf(y.w, ri)};
+    return r;
+  }
+  static __device__ __forceinline__ B load_b(const float2* p, int kg) {
+    const uint4* q = reinterpret_cast<const uint4*>(p + 4 * kg);
+    const uint4 x = q[0], y = q[1];
+    B r;
+    r.hi = v4u{x.x, x.z, y.x, y.z};
+    r.lo = v4u{x.y, x.w, y.y, y.w};
+    return r;
+  }
+  static __device__ __forceinline__ B zero_b() {
+    B r;
+    r.hi = v4u{0u, 0u, 0u, 0u};
+    r.lo = v4u{0u, 0u, 0u, 0u};
+    return r;
+  }
+  static __device__ __forceinline__ v4f mma(A a, B b, v4f c) { return mfma_bf3(a.hi, a.lo, b.hi, b.lo, c); }
+};
+
+// Row stride (complex elements) of a k-contiguous operand with r valid k:
+// padded to whole K-steps plus a skew (one element for FP32, two for the
+// 16-byte split-BF16 loads) so the rows a fragment touches fall in
+// different LDS banks.
+template <bool BF>
+__host__ __device__ __forceinline__ int tk_kpad(int r) {
+  return BF ? (r + 15) & ~15 : (r + 1) & ~1;
+}
+template <bool BF>
+__host__ __device__ __forceinline__ int tk_stride(int r) {
+  return BF ? tk_kpad<BF>(r) + 2 : tk_kpad<BF>(r) + 1;
+}
+__host__ __device__ __forceinline__ int tk_align4(int e) { return (e + 3) & ~3; }
+
+// LDS layout (complex elements) of the Tucker restoration of a tile with nfx
+// x-rows: U1 rows, U2, U3 columns of the chunk (pair), C chunk, W1 chunk.
+struct TuckerLds {
+  int s1, s2, fs, oU1, oU2, oV, oC, oW1, total;
+  template <bool BF>
+  __host__ __device__ __forceinline__ void plan(int nfx, int n2, int n3, int r1, int r2) {
+    s1 = tk_stride<BF>(r1);
+    s2 = tk_stride<BF>(r2);
+    fs = 8 * s2 + 2;  // W1 x-row stride, skewed against the 16 x-rows of a GEMM tile
+    oU1 = 0;
+    oU2 = tk_align4(oU1 + nfx * s1);
+    oV = tk_align4(oU2 + n2 * s2);
+    oC = tk_align4(oV + 8 * n3);
+    oW1 = tk_align4(oC + 8 * r2 * s1);
+    total = tk_align4(oW1 + nfx * fs);
+  }
+};
+
+// D0 += A . B0 and (if two) D1 += A . B1 over ks K-steps, A shared.  Steps
+// are taken in blocks of U with every fragment load of a block issued before
+// its MFMAs, so LDS latency overlaps the matrix-core work.
+template <bool BF, int U, bool TWO>
+__device__ __forceinline__ void tk_kloop(const float2* pa, const float2* pb0, const float2* pb1, int ks, v4f& D0,
+                                         v4f& D1) {
+  typedef Cx<BF> X;
+  const int l = threadIdx.x & 63, kg = l >> 4, ri = l & 1;
+  int s = 0;
+  for (; s + U <= ks; s += U) {
+    typename X::A av[U];
+    typename X::B b0[U], b1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = X::load_a(pa + (s + u) * X::KS, kg, ri);
+      b0[u] = X::load_b(pb0 + (s + u) * X::KS, kg);
+      if constexpr (TWO) b1[u] = X::load_b(pb1 + (s + u) * X::KS, kg);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      D0 = X::mma(av[u], b0[u], D0);
+      if constexpr (TWO) D1 = X::mma(av[u], b1[u], D1);
+    }
+  }
+  for (; s < ks; ++s) {
+    const typename X::A av = X::load_a(pa + s * X::KS, kg, ri);
+    D0 = X::mma(av, X::load_b(pb0 + s * X::KS, kg), D0);
+    if constexpr (TWO) D1 = X::mma(av, X::load_b(pb1 + s * X::KS, kg), D1);
+  }
+}
+
+// Second product for one column block of 16 pencils (lane j owns pencil q_j
+// with x-row fx_j of the tile and y-row fy_j).  A block whose pencils span
+// two x-rows is done in two passes, each with the other row's lanes masked.
+template <bool BF>
+__device__ __forceinline__ v4f tk_wgemm(const float2* sW1, const float2* sU2, int s2, int fs, int ks2, int fxa, int fxb,
+                                        int fxj, int fyj) {
+  typedef Cx<BF> X;
+  const int l = threadIdx.x & 63, kg = l >> 4, i = l & 15;
+  v4f D = {0.f, 0.f, 0.f, 0.f};
+  const float2* pb = sU2 + fyj * s2;
+  for (int seg = fxa; seg <= fxb; ++seg) {
+    const float2* pa = sW1 + seg * fs + (i >> 1) * s2;
+    const bool mine = fxj == seg;
+    for (int s = 0; s < ks2; ++s) {
+      const typename X::A av = X::load_a(pa + s * X::KS, kg, i & 1);
+      const typename X::B bv = mine ? X::load_b(pb + s * X::KS, kg) : X::zero_b();
+      D = X::mma(av, bv, D);
+    }
+  }
+  return D;
+}
+
+// Two column blocks with the same single x-row share the A fragments.
+template <bool BF>
+__device__ __forceinline__ void tk_wgemm2(const float2* sW1, const float2* sU2, int s2, int fs, int ks2, int fx, int fy0,
+                                          int fy1, v4f& D0, v4f& D1) {
+  const int i = threadIdx.x & 15;
+  D0 = v4f{0.f, 0.f, 0.f, 0.f};
+  D1 = v4f{0.f, 0.f, 0.f, 0.f};
+  tk_kloop<BF, BF ? 1 : 4, true>(sW1 + fx * fs + (i >> 1) * s2, sU2 + fy0 * s2, sU2 + fy1 * s2, ks2, D0, D1);
+}
+
+// Core chunk source: element e = (a*r2 + b)*8 + cl  <-  C[a][b][c0 + cl],
+// staged at LDS row 8b + cl, column a.  a = ab / r2 is taken as a multiply-
+// high by m = ceil(2^32 / r2), exact for ab < 2^16 and r2 <= 64.
+struct TkCoreSrc {
+  const float2* C;
+  int r2, r3;
+  unsigned m;
+  __device__ __forceinline__ float2 at(int e, int c0, int kc) const {
+    const int cl = e & 7, ab = e >> 3;
+    return cl < kc ? C[c0 + ab * r3 + cl] : make_float2(0.f, 0.f);
+  }
+  __device__ __forceinline__ int lds_index(int e, int s1) const {
+    const int cl = e & 7, ab = e >> 3, a = (int)__umulhi((unsigned)ab, m), b = ab - a * r2;
+    return (8 * b + cl) * s1 + a;
+  }
+};
+
+template <int T, int CB, int NW, bool BF>
+__device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a, const int* d, int q0,
+                                               float2* lds) {
+  typedef Cx<BF> X;
+  constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T, PF = 4;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, kg = l >> 4, i = l & 15, j = l & 15;
+  const int n2 = a.n2;
+  const int r1 = d[4], r2 = d[5], r3 = d[6];
+  const float2* C = a.cbase + d[0];
+  const float2* U1 = a.fbase + d[1];
+  const float2* U2 = a.fbase + d[2];
+  const float2* U3 = a.fbase + d[3];
+  const int nfx = QT / n2, fx0 = q0 / n2;
+  TuckerLds L;
+  L.plan<BF>(nfx, n2, N3, r1, r2);
+  const int s1 = L.s1, s2 = L.s2, fs = L.fs, kp1 = tk_kpad<BF>(r1), kp2 = tk_kpad<BF>(r2);
+  const int ks1 = kp1 / X::KS, ks2 = kp2 / X::KS;
+  float2* sU1 = lds + L.oU1;
+  float2* sU2 = lds + L.oU2;
+  float2* sV = lds + L.oV;
+  float2* sC = lds + L.oC;
+  float2* sW1 = lds + L.oW1;
+
+  // factors, and the zero padding of the C and W1 chunk rows (never rewritten)
+  for (int e = tid; e < nfx * kp1; e += NT) {
+    const int fx = e / kp1, k = e - fx * kp1;
+    stage<BF>(sU1, fx * s1 + k, k < r1 ? U1[(long long)(fx0 + fx) * r1 + k] : make_float2(0.f, 0.f));
+  }
+  for (int e = tid; e < n2 * kp2; e += NT) {
+    const int fy = e / kp2, k = e - fy * kp2;
+    stage<BF>(sU2, fy * s2 + k, k < r2 ? U2[fy * r2 + k] : make_float2(0.f, 0.f));
+  }
+  if (kp1 > r1)
+    for (int e = tid; e < 8 * r2 * (kp1 - r1); e += NT) {
+      const int row = e / (kp1 - r1);
+      stage<BF>(sC, row * s1 + r1 + (e - row * (kp1 - r1)), make_float2(0.f, 0.f));
+    }
+  if (kp2 > r2)
+    for (int e = tid; e < 8 * nfx * (kp2 - r2); e += NT) {
+      const int row = e / (kp2 - r2);
+      stage<BF>(sW1, (row >> 3) * fs + (row & 7) * s2 + r2 + (e - row * (kp2 - r2)), make_float2(0.f, 0.f));
+    }
+
+  // Core chunks are staged through registers in parts of PF elements per
+  // thread, one part in flight at a time: part 0 (with the U3 columns) is
+  // loaded during the first product and stored after it; the later parts are
+  // loaded and stored between column-block pairs of the second/third
+  // products, so their latency hides behind matrix-core work.
+  const TkCoreSrc src{C, r2, r3, (unsigned)(((1ull << 32) + (unsigned)r2 - 1) / (unsigned)r2)};
+  const int csz = 8 * r2 * r1;
+  constexpr int PART = PF * NT, VP = (8 * N3 + NT - 1) / NT;
+  const int nparts = (csz + PART - 1) / PART;
+  float px[PF], py[PF], vx[VP], vy[VP];
+  auto load_part = [&](int P, int c0) {
+    const int kc = min(8, r3 - c0);
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = P * PART + tid + u * NT;
+      const float2 v = e < csz ? src.at(e, c0, kc) : make_float2(0.f, 0.f);
+      px[u] = v.x;
+      py[u] = v.y;
+    }
+  };
+  auto store_part = [&](int P) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = P * PART + tid + u * NT;
+      if (e < csz) stage<BF>(sC, src.lds_index(e, s1), make_float2(px[u], py[u]));
+    }
+  };
+  auto load_v = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < VP; ++u) {
+      const int e = tid + u * NT, fz = e >> 3, cl = e & 7;
+      const float2 v = (e < 8 * N3 && c0 + cl < r3) ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f);
+      vx[u] = v.x;
+      vy[u] = v.y;
+    }
+  };
+  auto store_v = [&]() {
+#pragma unroll
+    for (int u = 0; u < VP; ++u) {
+      const int e = tid + u * NT;
+      if (e < 8 * N3) stage<BF>(sV, e, make_float2(vx[u], vy[u]));
+    }
+  };
+  load_v(0);
+  store_v();
+  for (int P = 0; P < nparts; ++P) {
+    load_part(P, 0);
+    store_part(P);
+  }
+  __syncthreads();
+
+  // third-product A fragments of the chunk: FP32 4 steps x 1 float; BF16X3
+  // [hi(c0), hi(c1), lo(c0), lo(c1)] of the embedded U3 entries, c0 = 2kg
+  float a3f[T][BF ? 1 : 4];
+  v4u a3b[T];
+  const int nch = (r3 + 7) >> 3;
+  for (int h = 0; h < nch; ++h) {
+    const int c0 = 8 * h;
+    const bool more = h + 1 < nch;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int fz = 8 * t + (i >> 1), ri = i & 1;
+      if constexpr (BF) {
+        const uint2* pv = reinterpret_cast<const uint2*>(sV) + fz * 8 + 2 * kg;
+        const uint2 v0 = pv[0], v1 = pv[1];
+        a3b[t] = v4u{embed_a_bf(v0.x, ri), embed_a_bf(v1.x, ri), embed_a_bf(v0.y, ri), embed_a_bf(v1.y, ri)};
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) a3f[t][s4] = embed_a(sV[fz * 8 + 2 * kg + (s4 >> 1)], ri, s4 & 1);
+      }
+    }
+    if (more) {
+      load_part(0, c0 + 8);
+      load_v(c0 + 8);
+    }
+    // first product, block-wide: W1^T[(b,cl)][fx] = sum_a C^T[(b,cl)][a] U1^T[a][fx];
+    // a task is one b (8 rows of C^T) against up to two 16-column fx tiles
+    {
+      const int fxc0 = min(j, nfx - 1), fxc1 = min(16 + j, nfx - 1);
+      const float2* pb0 = sU1 + fxc0 * s1;
+      const float2* pb1 = sU1 + fxc1 * s1;
+      for (int b = w; b < r2; b += NW) {
+        const float2* pa = sC + (8 * b + (i >> 1)) * s1;
+        v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
+        if (nfx > 16)
+          tk_kloop<BF, BF ? 1 : 4, true>(pa, pb0, pb1, ks1, D0, D1);
+        else
+          tk_kloop<BF, BF ? 1 : 4, false>(pa, pb0, pb1, ks1, D0, D1);
+        if (j < nfx) {
+          stage<BF>(sW1, j * fs + 2 * kg * s2 + b, make_float2(D0[0], D0[1]));
+          stage<BF>(sW1, j * fs + (2 * kg + 1) * s2 + b, make_float2(D0[2], D0[3]));
+        }
+        if (16 + j < nfx) {
+          stage<BF>(sW1, (16 + j) * fs + 2 * kg * s2 + b, make_float2(D1[0], D1[1]));
+          stage<BF>(sW1, (16 + j) * fs + (2 * kg + 1) * s2 + b, make_float2(D1[2], D1[3]));
+        }
+      }
+    }
+    __syncthreads();
+    int part = 0;  // part of the next chunk currently in registers
+    if (more) {
+      store_part(0);
+      store_v();
+      if (++part < nparts) load_part(part, c0 + 8);
+    }
+    // second and third products, per wave
+    auto finish = [&](int c, v4f D) {
+      if constexpr (BF) {
+        // [A_hi, A_lo] . [W_hi; W_hi] + [A_hi, A_lo] . [W_lo; 0]
+        const uint2 e0 = split_bf3(make_float2(D[0], D[1])), e1 = split_bf3(make_float2(D[2], D[3]));
+        const v4u bh = v4u{e0.x, e1.x, e0.x, e1.x}, bl = v4u{e0.y, e1.y, 0u, 0u};
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          acc[t][c] = mfma_bf16(a3b[t], bh, acc[t][c]);
+          acc[t][c] = mfma_bf16(a3b[t], bl, acc[t][c]);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) acc[t][c] = mfma4(a3f[t][s4], D[s4], acc[t][c]);
+      }
+    };
+#pragma unroll
+    for (int c = 0; c < CB; c += 2) {
+      // pencils of blocks c and c+1: x-row of lane 0 (fa), of lane 15 (fb); a
+      // block spans at most two x-rows since n2 >= 8
+      int fa[2], fb[2], fxj[2], fyj[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int qb = q0 + (w * CB + min(c + u, CB - 1)) * 16;
+        const int xa = qb / n2, off = qb - xa * n2 + j, wrap = off >= n2 ? 1 : 0;
+        fa[u] = xa - fx0;
+        fb[u] = (qb + 15) / n2 - fx0;
+        fxj[u] = fa[u] + wrap;
+        fyj[u] = off - wrap * n2;
+      }
+      if (c + 1 < CB && fa[0] == fb[0] && fa[1] == fb[1] && fa[0] == fa[1]) {
+        v4f D0, D1;
+        tk_wgemm2<BF>(sW1, sU2, s2, L.fs, ks2, fa[0], fyj[0], fyj[1], D0, D1);
+        finish(c, D0);
+        finish(c + 1, D1);
+      } else {
+        finish(c, tk_wgemm<BF>(sW1, sU2, s2, L.fs, ks2, fa[0], fb[0], fxj[0], fyj[0]));
+        if (c + 1 < CB) finish(c + 1, tk_wgemm<BF>(sW1, sU2, s2, L.fs, ks2, fa[1], fb[1], fxj[1], fyj[1]));
+      }
+      if (more && part < nparts) {
+        store_part(part);
+        if (++part < nparts) load_part(part, c0 + 8);
+      }
+    }
+    while (more && part < nparts) {
+      store_part(part);
+      if (++part < nparts) load_part(part, c0 + 8);
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace tfmm
