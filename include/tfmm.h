@@ -127,10 +127,16 @@ typedef struct {
 
 /* Create a context on HIP device `device` with a device-memory budget for
  * operators and translation scratch (0 => 90% of the device's free memory).
- * Fails with TFMM_ERR_NO_DEVICE when no device is visible.  With the
- * environment variable TFMM_NO_FUSED=1 at creation, operators of this context
- * always use the three-pass kernel pipeline instead of the fused
- * one-kernel-per-direction path available for cubic grids up to 16^3 boxes. */
+ * Fails with TFMM_ERR_NO_DEVICE when no device is visible.  Environment
+ * variables read at creation select implementation variants (results agree
+ * within FP32 rounding):
+ *   TFMM_NO_FUSED=1  always use the three-pass kernel pipeline instead of the
+ *                    fused one-kernel-per-direction path available for cubic
+ *                    grids up to 16^3 boxes;
+ *   TFMM_NO_TK2=1    restore Tucker-family operators through LDS-staged
+ *                    products instead of the register-chained restoration;
+ *   TFMM_GRAPH=0|1   never / always replay tfmm_translate from a captured
+ *                    hipGraph (default: only multi-launch translations). */
 tfmm_status tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx* out);
 
 /* Wait for every submitted job, stop the scheduler, free all operators and
@@ -193,8 +199,14 @@ tfmm_status tfmm_op_release(tfmm_ctx ctx, tfmm_op op);
  * complex64 arrays [nrhs][n_dir][Kx][Ky][Kz], caller-owned; they must not
  * alias and must stay valid until the stream reaches the end of the work.
  * Translation scratch comes from the context (charged to its budget on first
- * use and kept); concurrent translations on one context are serialised on
- * scratch by the context mutex and the stream order. */
+ * use and kept) and is shared by every tfmm_translate call of the context:
+ * calls on different streams must not overlap on the device.  The first call
+ * for a given (op, nrhs, A, B) runs eagerly and records the launch sequence in
+ * a hipGraph that later calls with the same arguments replay (see
+ * TFMM_GRAPH); at most four graphs are kept per operator, and a graph is
+ * dropped when the scratch it uses moves.  The kernels are persistent: they
+ * take (direction, pencil tile) work items from a device counter, costliest
+ * directions first, so results do not depend on the launch shape. */
 tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
                            void* hip_stream);
 
@@ -215,6 +227,30 @@ tfmm_status tfmm_poll(tfmm_ctx ctx, tfmm_ticket t, int32_t* done, tfmm_status* j
 
 /* Block until the job is done; the ticket is then retired. */
 tfmm_status tfmm_wait(tfmm_ctx ctx, tfmm_ticket t, tfmm_status* job_status, double* latency_us);
+
+/* ---- batching: tile autotuner ------------------------------------------------ */
+
+/* Time every tile configuration the operator's grid admits (fused
+ * one-kernel path vs three-pass pipeline, three-pass pencil tile of 64*cb
+ * pencils, and for Tucker-family operators the register-chained vs
+ * LDS-staged restoration) on `nrhs` right-hand sides, `reps` timed runs each
+ * (median of HIP-event durations on an internal stream, after two warm-up
+ * runs), and adopt the fastest for this operator.  Temporary A/B buffers
+ * (2 x nrhs x n_dir x Kx x Ky x Kz complex64) are charged to the budget for
+ * the duration of the call.  The choice is remembered by the context under a
+ * key of (format, precision, FFT grid, direction count, maximum rank rounded up
+ * to 8, RHS bucket 1 | 2-4 | 5-16 | >16); later translations of any operator
+ * with the same key use it, and with TFMM_TUNE_CACHE=<path> set at context
+ * creation the choices are read from and appended to that text file.
+ * `choice_out` (may be NULL) receives {fused 0/1, cb, register-chained 0/1};
+ * `best_ms` (may be NULL) the winning median.  TFMM_ERR_BUSY while submitted
+ * jobs use the operator. */
+tfmm_status tfmm_autotune(tfmm_ctx ctx, tfmm_op op, int32_t nrhs, int32_t reps, int32_t* choice_out,
+                          double* best_ms);
+
+/* The operator's current plan: {fused 0/1, three-pass cb, register-chained
+ * restoration 0/1, 1 if chosen by the autotuner}; writes min(cap, 4) values. */
+tfmm_status tfmm_op_plan(tfmm_op op, int32_t* out, size_t cap);
 
 /* ---- diagnostics ------------------------------------------------------------ */
 

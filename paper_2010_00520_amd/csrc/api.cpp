@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -62,6 +63,13 @@ struct ScratchSlot {
   size_t bytes = 0;
 };
 
+// A tile-configuration choice of the autotuner: -1 / 0 = keep the default.
+struct TuneChoice {
+  int fused = -1;  // 1: fused one-kernel path (when the grid allows), 0: three-pass
+  int cb = 0;      // three-pass pencil tile: 64*cb pencils per block
+  int tk2 = -1;    // Tucker family: 1 register-chained, 0 LDS-staged restoration
+};
+
 struct tfmm_op_s {
   tfmm_ctx ctx = nullptr;
   tfmm_format fmt = TFMM_FMT_FULL;
@@ -83,6 +91,19 @@ struct tfmm_op_s {
   // Tucker family: register-chained restoration (3-pass tile / fused tile)
   bool tk2 = false, ftk2 = false;
   size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
+  int* d_perm = nullptr;               // direction order, costliest restoration first (NULL: identity)
+  // captured translations, keyed by (nrhs, A, B) and the scratch generation
+  struct GraphEntry {
+    int nrhs;
+    const void* A;
+    void* B;
+    unsigned gen;
+    hipGraph_t g;
+    hipGraphExec_t x;
+  };
+  std::vector<GraphEntry> graphs;      // least recently used first
+  TuneChoice choice;                   // plan overrides in effect
+  bool tuned = false;                  // choice came from the autotuner or its cache
   tfmm_op_info info{};
   std::atomic<int> refs{0};
 };
@@ -118,6 +139,16 @@ struct tfmm_ctx_s {
   // translation scratch, one per stream slot (slot 0 = tfmm_translate; 1..S = scheduler streams)
   static constexpr int kSlots = 3;
   ScratchSlot scratch[kSlots];
+  unsigned scratch_gen[kSlots] = {0, 0, 0};  // bumped when a slot's buffer moves
+  int* counters = nullptr;             // device work counters of the persistent launches, one per slot
+  int ncu = 0;                         // compute units
+  hipStream_t cap_stream = nullptr;    // stream used only for graph capture
+  // graph policy (TFMM_GRAPH): 0 never capture, 1 always, 2 (default) only
+  // multi-launch translations; TFMM_NO_GRAPH=1 is the same as 0
+  int graph_mode = 2;
+  // autotuner results: key -> choice, loaded from / appended to TFMM_TUNE_CACHE
+  std::map<std::string, TuneChoice> tune;
+  std::string tune_path;
   std::map<int, float2*> roots;        // n3 -> device table exp(-2 pi i m/n3)
   // profiling
   bool prof = false;
@@ -202,6 +233,7 @@ tfmm_status ensure_scratch(tfmm_ctx c, int slot, size_t bytes, void** out) {
       want = bytes;
     }
     s.bytes = want;
+    ++c->scratch_gen[slot];
   }
   *out = s.ptr;
   return TFMM_OK;
@@ -255,11 +287,21 @@ int pick_cb(int n2, int nq, int max_cb) {
   return 0;
 }
 
+int max_cb_for(int n3) {
+  // accumulator registers: (n3/8) * cb * 4 per lane; keep them <= 96
+  return n3 >= 64 ? 2 : (n3 >= 48 ? 3 : 4);
+}
+
+bool cb_valid(int cb, int n2, int nq, int n3) {
+  const int qt = 64 * cb;
+  return cb >= 1 && cb <= max_cb_for(n3) && qt % n2 == 0 && nq % qt == 0;
+}
+
 tfmm_status plan_zstage(tfmm_op op) {
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2];
   op->nq = n1 * n2;
-  // accumulator registers: (n3/8) * cb * 4 per lane; keep them <= 96
-  op->cb = pick_cb(n2, op->nq, n3 >= 64 ? 2 : (n3 >= 48 ? 3 : 4));
+  const TuneChoice& ch = op->choice;
+  op->cb = cb_valid(ch.cb, n2, op->nq, n3) ? ch.cb : pick_cb(n2, op->nq, max_cb_for(n3));
   if (op->cb == 0) return fail(TFMM_ERR_UNSUPPORTED, "no pencil tiling for this grid");
   switch (op->fmt) {
     case TFMM_FMT_FULL: op->zfmt = tfmm::ZF_FULL; break;
@@ -275,7 +317,7 @@ tfmm_status plan_zstage(tfmm_op op) {
       r1 = std::max(r1, op->desc[8 * p + 4]);
       r2 = std::max(r2, op->desc[8 * p + 5]);
     }
-  const size_t lds_max = 160 * 1024;
+  const size_t lds_max = 160 * 1024 - 64;  // leaves room for the work-item slot
   const bool bf = op->prec == TFMM_PREC_BF16X3;
   op->tk2 = op->ftk2 = false;
   if (op->zfmt != tfmm::ZF_FULL) {
@@ -283,7 +325,7 @@ tfmm_status plan_zstage(tfmm_op op) {
     int KC = 16;
     while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2) > cap) KC /= 2;
     size_t need = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2);
-    if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2) {
+    if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2 && ch.tk2 != 0) {
       const size_t need2 = tfmm::tucker2_lds_bytes(n2, n3, 64 * op->cb, r1, r2, bf);
       if (need2 <= lds_max) {
         op->tk2 = true;
@@ -296,7 +338,8 @@ tfmm_status plan_zstage(tfmm_op op) {
   }
   // fused path: cubic grids whose half spectrum (n*n*zp complex64) fits in LDS
   op->fused = false;
-  if (!op->ctx->no_fused && n1 == n2 && n2 == n3 && (n1 == 8 || n1 == 16 || n1 == 24 || n1 == 32)) {
+  if (!op->ctx->no_fused && ch.fused != 0 && n1 == n2 && n2 == n3 &&
+      (n1 == 8 || n1 == 16 || n1 == 24 || n1 == 32)) {
     const int K3 = n3 / 2, zp = (K3 & 1) ? K3 : K3 + 1;
     const size_t hbytes = (size_t)n1 * n2 * zp * sizeof(float2);
     int KC = 16;
@@ -305,7 +348,7 @@ tfmm_status plan_zstage(tfmm_op op) {
     if (op->zfmt != tfmm::ZF_FULL) {
       while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2) > lds_max) KC /= 2;
       rb = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2);
-      if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2) {
+      if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2 && ch.tk2 != 0) {
         const size_t rb2 = tfmm::tucker2_lds_bytes(n2, n3, n1 * n2, r1, r2, bf);
         if (rb2 <= lds_max) {
           ftk2 = true;
@@ -406,6 +449,25 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
   if (s != TFMM_OK) return s;
   op->dev_bytes += op->desc.size() * sizeof(int);
   HIP_TRY(hipMemcpy(op->d_desc, op->desc.data(), op->desc.size() * sizeof(int), hipMemcpyHostToDevice));
+  // 3-D formats have per-direction ranks: launch the costliest restorations
+  // first so the persistent grids finish evenly
+  if (op->fmt == TFMM_FMT_TUCKER3D || op->fmt == TFMM_FMT_TT3D) {
+    std::vector<double> cost(nd);
+    for (int p = 0; p < nd; ++p) {
+      const int* d = &op->desc[8 * p];
+      const double r1 = d[4], r2 = d[5], r3 = d[6];
+      cost[p] = op->fmt == TFMM_FMT_TUCKER3D
+                    ? n1 * r1 * r2 * r3 + (double)n1 * n2 * r2 * r3 + (double)n1 * n2 * n3 * r3
+                    : n1 * r1 * n2 * r2 + (double)n1 * n2 * n3 * r2;
+    }
+    std::vector<int> perm(nd);
+    for (int p = 0; p < nd; ++p) perm[p] = p;
+    std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    s = dev_alloc(c, (void**)&op->d_perm, (size_t)nd * sizeof(int));
+    if (s != TFMM_OK) return s;
+    op->dev_bytes += (size_t)nd * sizeof(int);
+    HIP_TRY(hipMemcpy(op->d_perm, perm.data(), (size_t)nd * sizeof(int), hipMemcpyHostToDevice));
+  }
   return plan_zstage(op);
 }
 
@@ -479,6 +541,11 @@ void free_op(tfmm_ctx c, tfmm_op op) {
   if (op->d_full) dev_free(c, op->d_full, (size_t)op->ndir * op->n[0] * op->n[1] * op->n[2] * 8);
   if (op->d_data) dev_free(c, op->d_data, op->stored_elems * sizeof(float2));
   if (op->d_desc) dev_free(c, op->d_desc, op->desc.size() * sizeof(int));
+  if (op->d_perm) dev_free(c, op->d_perm, (size_t)op->ndir * sizeof(int));
+  for (auto& e : op->graphs) {
+    (void)hipGraphExecDestroy(e.x);
+    (void)hipGraphDestroy(e.g);
+  }
   delete op;
 }
 
@@ -598,6 +665,9 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   z.lds_bytes = op->lds;
   z.bf = op->prec == TFMM_PREC_BF16X3 ? 1 : 0;
   z.tk2 = op->tk2 ? 1 : 0;
+  z.perm = op->d_perm;
+  z.counter = c->counters + 2 * slot;
+  z.ncu = c->ncu;
   const float scale = 1.0f / (float)((double)n1 * n2 * n3);
   if (op->fused) {
     z.KC = op->fKC;
@@ -633,7 +703,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
       bool ok = false;
       {
         Launch L(c, st, "fwd_xy");
-        HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, twx, st, &ok));
+        HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, twx, st, &ok));
         L.done();
       }
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "xy-FFT sizes unsupported");
@@ -648,7 +718,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "z-stage size unsupported");
       {
         Launch L(c, st, "inv_xy");
-        HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, scale, twx, st, &ok));
+        HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, scale, twx, st, &ok));
         L.done();
       }
     }
@@ -656,8 +726,66 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   return TFMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: tile configurations keyed by grid class, rank bucket, precision
+// and RHS bucket.
+// ---------------------------------------------------------------------------
+std::string tune_key(tfmm_op op, int nrhs) {
+  int rmax = 0;
+  for (int32_t r : op->host.ranks) rmax = std::max(rmax, (int)r);
+  const int nb = nrhs <= 1 ? 1 : (nrhs <= 4 ? 4 : (nrhs <= 16 ? 16 : 64));
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "f%d|p%d|n%dx%dx%d|d%d|r%d|s%d", (int)op->fmt, (int)op->prec, op->n[0], op->n[1],
+                op->n[2], op->ndir, (rmax + 7) / 8 * 8, nb);
+  return buf;
+}
+
+bool same_choice(const TuneChoice& a, const TuneChoice& b) {
+  return a.fused == b.fused && a.cb == b.cb && a.tk2 == b.tk2;
+}
+
+void drop_graphs(tfmm_op op) {
+  for (auto& e : op->graphs) {
+    (void)hipGraphExecDestroy(e.x);
+    (void)hipGraphDestroy(e.g);
+  }
+  op->graphs.clear();
+}
+
+tfmm_status apply_choice(tfmm_op op, const TuneChoice& ch) {
+  if (same_choice(op->choice, ch)) return TFMM_OK;
+  const TuneChoice old = op->choice;
+  op->choice = ch;
+  tfmm_status s = plan_zstage(op);
+  if (s != TFMM_OK) {
+    op->choice = old;
+    (void)plan_zstage(op);
+    return s;
+  }
+  drop_graphs(op);
+  return TFMM_OK;
+}
+
+// Use the tuned configuration for this RHS count if one is known.
+void apply_tuned(tfmm_ctx c, tfmm_op op, int nrhs) {
+  if (c->tune.empty()) return;
+  auto it = c->tune.find(tune_key(op, nrhs));
+  if (it != c->tune.end() && apply_choice(op, it->second) == TFMM_OK) op->tuned = true;
+}
+
+void load_tune_cache(tfmm_ctx c) {
+  FILE* f = c->tune_path.empty() ? nullptr : std::fopen(c->tune_path.c_str(), "r");
+  if (!f) return;
+  char key[160];
+  TuneChoice ch;
+  while (std::fscanf(f, "%159s fused=%d cb=%d tk2=%d%*[^\n]", key, &ch.fused, &ch.cb, &ch.tk2) == 4)
+    c->tune[key] = ch;
+  std::fclose(f);
+}
+
 tfmm_status translate_contiguous(tfmm_ctx c, tfmm_op op, const void* A, void* B, int nrhs, hipStream_t st,
                                  int slot) {
+  apply_tuned(c, op, nrhs);
   const size_t blk = (size_t)op->ndir * op->K[0] * op->K[1] * op->K[2];
   std::vector<const float2*> As(nrhs);
   std::vector<float2*> Bs(nrhs);
@@ -809,6 +937,24 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   c->no_fused = nf && nf[0] == '1';
   const char* nt = std::getenv("TFMM_NO_TK2");
   c->no_tk2 = nt && nt[0] == '1';
+  const char* tp = std::getenv("TFMM_TUNE_CACHE");
+  if (tp && tp[0]) {
+    c->tune_path = tp;
+    load_tune_cache(c);
+  }
+  const char* gm = std::getenv("TFMM_GRAPH");
+  if (gm && (gm[0] == '0' || gm[0] == '1')) c->graph_mode = gm[0] - '0';
+  const char* ng = std::getenv("TFMM_NO_GRAPH");
+  if (ng && ng[0] == '1') c->graph_mode = 0;
+  if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->ncu < 1)
+    c->ncu = 1;
+  if (hipMalloc((void**)&c->counters, 64 * sizeof(int)) != hipSuccess ||
+      hipMemset(c->counters, 0, 64 * sizeof(int)) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    if (c->counters) (void)hipFree(c->counters);
+    delete c;
+    return fail(TFMM_ERR_HIP, "context resources could not be created");
+  }
   for (int i = 0; i < 2; ++i)
     if (hipStreamCreateWithFlags(&c->streams[i], hipStreamNonBlocking) != hipSuccess) {
       delete c;
@@ -843,6 +989,8 @@ tfmm_status tfmm_ctx_destroy(tfmm_ctx c) {
   for (auto& s : c->scratch)
     if (s.ptr) (void)hipFree(s.ptr);
   for (auto& s : c->streams) (void)hipStreamDestroy(s);
+  (void)hipStreamDestroy(c->cap_stream);
+  (void)hipFree(c->counters);
   delete c;
   return TFMM_OK;
 }
@@ -1011,7 +1159,55 @@ tfmm_status tfmm_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32
   if (s != TFMM_OK) return s;
   std::lock_guard<std::recursive_mutex> g(c->mu);
   HIP_TRY(hipSetDevice(c->device));
-  return translate_contiguous(c, op, A, B, nrhs, (hipStream_t)stream, 0);
+  hipStream_t st = (hipStream_t)stream;
+  // A single fused launch is cheaper to issue directly than as a graph;
+  // multi-launch sequences (three-pass pipeline, per-call core contraction)
+  // are captured once per (nrhs, A, B) and replayed.
+  const bool multi = !op->fused || op->a1_bytes > 0;
+  if (c->prof || c->graph_mode == 0 || (c->graph_mode == 2 && !multi))
+    return translate_contiguous(c, op, A, B, nrhs, st, 0);
+  // replay a captured translation of the same (nrhs, A, B) if its scratch is still in place
+  auto& G = op->graphs;
+  for (size_t i = 0; i < G.size(); ++i) {
+    if (G[i].nrhs != nrhs || G[i].A != A || G[i].B != B) continue;
+    tfmm_op_s::GraphEntry e = G[i];
+    G.erase(G.begin() + i);
+    if (e.gen == c->scratch_gen[0]) {
+      G.push_back(e);
+      HIP_TRY(hipGraphLaunch(e.x, st));
+      return TFMM_OK;
+    }
+    (void)hipGraphExecDestroy(e.x);
+    (void)hipGraphDestroy(e.g);
+    break;
+  }
+  // first use: run eagerly (this also sizes scratch and tables), then record the
+  // same launch sequence on the capture stream for later calls
+  s = translate_contiguous(c, op, A, B, nrhs, st, 0);
+  if (s != TFMM_OK) return s;
+  const unsigned gen = c->scratch_gen[0];
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+  s = translate_contiguous(c, op, A, B, nrhs, c->cap_stream, 0);
+  hipGraph_t gr = nullptr;
+  const hipError_t ce = hipStreamEndCapture(c->cap_stream, &gr);
+  if (s != TFMM_OK || ce != hipSuccess || gen != c->scratch_gen[0]) {
+    if (gr) (void)hipGraphDestroy(gr);
+    (void)hipGetLastError();
+    return s;  // the eager result stands; capture is retried on the next call
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, gr, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    (void)hipGetLastError();
+    return TFMM_OK;
+  }
+  if (G.size() >= 4) {
+    (void)hipGraphExecDestroy(G.front().x);
+    (void)hipGraphDestroy(G.front().g);
+    G.erase(G.begin());
+  }
+  G.push_back({nrhs, A, B, gen, gr, x});
+  return TFMM_OK;
 }
 
 tfmm_status tfmm_submit(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs, tfmm_ticket* out) {
@@ -1119,3 +1315,95 @@ tfmm_status tfmm_kernel_times(tfmm_ctx c, char* names, size_t names_cap, double*
 }
 
 }  // extern "C"
+
+tfmm_status tfmm_op_plan(tfmm_op op, int32_t* out, size_t cap) {
+  if (!op || !out) return fail(TFMM_ERR_INVALID_ARG, "op or out is NULL");
+  const int32_t v[4] = {op->fused ? 1 : 0, op->cb, (op->fused ? op->ftk2 : op->tk2) ? 1 : 0, op->tuned ? 1 : 0};
+  for (size_t i = 0; i < cap && i < 4; ++i) out[i] = v[i];
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_autotune(tfmm_ctx c, tfmm_op op, int32_t nrhs, int32_t reps, int32_t* choice_out, double* best_ms) {
+  if (!c || !op) return fail(TFMM_ERR_INVALID_ARG, "ctx or op is NULL");
+  if (op->ctx != c) return fail(TFMM_ERR_INVALID_ARG, "operator belongs to another context");
+  if (nrhs < 1 || nrhs > 4096) return fail(TFMM_ERR_INVALID_ARG, "nrhs out of range");
+  if (reps < 1 || reps > 200) return fail(TFMM_ERR_INVALID_ARG, "reps must be in 1..200");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  if (op->refs.load() > 0) return fail(TFMM_ERR_BUSY, "operator has queued jobs");
+  HIP_TRY(hipSetDevice(c->device));
+  const size_t bytes = (size_t)nrhs * op->ndir * op->K[0] * op->K[1] * op->K[2] * sizeof(float2);
+  void *A = nullptr, *B = nullptr;
+  tfmm_status s = dev_alloc(c, &A, bytes);
+  if (s != TFMM_OK) return s;
+  s = dev_alloc(c, &B, bytes);
+  if (s != TFMM_OK) {
+    dev_free(c, A, bytes);
+    return s;
+  }
+  HIP_TRY(hipMemset(A, 0x3c, bytes));  // any finite pattern: the kernels' cost does not depend on values
+  // candidates
+  const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nq = n1 * n2;
+  const bool tucker = op->zfmt == tfmm::ZF_TUCKER;
+  const bool fusable = !c->no_fused && n1 == n2 && n2 == n3 && (n1 == 8 || n1 == 16 || n1 == 24 || n1 == 32);
+  std::vector<TuneChoice> cand;
+  for (int tk : tucker ? std::vector<int>{1, 0} : std::vector<int>{-1}) {
+    if (fusable) cand.push_back({1, 0, tk});
+    for (int cb = 1; cb <= 4; ++cb)
+      if (cb_valid(cb, n2, nq, n3)) cand.push_back({0, cb, tk});
+  }
+  const bool prof = c->prof;
+  c->prof = false;
+  const TuneChoice start = op->choice;
+  hipStream_t st = c->cap_stream;
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto& e : ev) (void)hipEventCreate(&e);
+  double best = 1e300;
+  TuneChoice pick = start;
+  for (const TuneChoice& ch : cand) {
+    if (apply_choice(op, ch) != TFMM_OK) continue;
+    bool ok = true;
+    for (int w = 0; w < 2 && ok; ++w) ok = translate_contiguous(c, op, A, B, nrhs, st, 0) == TFMM_OK;
+    for (int r = 0; r < reps && ok; ++r) {
+      ok = hipEventRecord(ev[2 * r], st) == hipSuccess;
+      ok = ok && translate_contiguous(c, op, A, B, nrhs, st, 0) == TFMM_OK;
+      ok = ok && hipEventRecord(ev[2 * r + 1], st) == hipSuccess;
+    }
+    if (!ok || hipStreamSynchronize(st) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    std::vector<float> t(reps);
+    for (int r = 0; r < reps; ++r) (void)hipEventElapsedTime(&t[r], ev[2 * r], ev[2 * r + 1]);
+    std::nth_element(t.begin(), t.begin() + reps / 2, t.end());
+    if (t[reps / 2] < best) {
+      best = t[reps / 2];
+      pick = ch;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  c->prof = prof;
+  dev_free(c, A, bytes);
+  dev_free(c, B, bytes);
+  if (best >= 1e300) {
+    (void)apply_choice(op, start);
+    return fail(TFMM_ERR_INTERNAL, "no tile configuration ran");
+  }
+  s = apply_choice(op, pick);
+  if (s != TFMM_OK) return s;
+  op->tuned = true;
+  const std::string key = tune_key(op, nrhs);
+  c->tune[key] = pick;
+  if (!c->tune_path.empty()) {
+    if (FILE* f = std::fopen(c->tune_path.c_str(), "a")) {
+      std::fprintf(f, "%s fused=%d cb=%d tk2=%d ms=%.6f\n", key.c_str(), pick.fused, pick.cb, pick.tk2, best);
+      std::fclose(f);
+    }
+  }
+  if (choice_out) {
+    choice_out[0] = op->fused ? 1 : 0;
+    choice_out[1] = op->cb;
+    choice_out[2] = (op->fused ? op->ftk2 : op->tk2) ? 1 : 0;
+  }
+  if (best_ms) *best_ms = best;
+  return TFMM_OK;
+}

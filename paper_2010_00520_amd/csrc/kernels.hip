@@ -118,11 +118,13 @@ hipError_t launch_pack_full(const float2* src, float4* dst, int ndir, int nq, in
 // ---------------------------------------------------------------------------
 template <int N1, int N2>
 __global__ __launch_bounds__(TFMM_BLOCK) void k_fwd_xy(RhsPtrs P, float2* __restrict__ H, int K3, int zg, int zp,
-                                                       int ndl, int p0, const float2* __restrict__ twx) {
+                                                       int ndl, int p0, const int* __restrict__ perm,
+                                                       const float2* __restrict__ twx) {
   extern __shared__ float2 lds[];
   constexpr int K1 = N1 / 2, K2 = N2 / 2, NQ = N1 * N2;
   const int s = blockIdx.z, pl = blockIdx.y, z0 = blockIdx.x * zg;
-  const float2* __restrict__ Ab = P.a[s] + (long long)(p0 + pl) * ((long long)K1 * K2 * K3);
+  const int p = perm ? perm[p0 + pl] : p0 + pl;
+  const float2* __restrict__ Ab = P.a[s] + (long long)p * ((long long)K1 * K2 * K3);
   xy_forward<N1, N2, TFMM_BLOCK>(lds, Ab, K3, zg, zp, z0, twx);
   __syncthreads();
   float2* Hb = H + ((long long)s * ndl + pl) * ((long long)K3 * NQ) + (long long)z0 * NQ;
@@ -134,8 +136,8 @@ __global__ __launch_bounds__(TFMM_BLOCK) void k_fwd_xy(RhsPtrs P, float2* __rest
 
 template <int N1, int N2>
 __global__ __launch_bounds__(TFMM_BLOCK) void k_inv_xy(RhsPtrs P, const float2* __restrict__ H, int K3, int zg,
-                                                       int zp, int ndl, int p0, float scale,
-                                                       const float2* __restrict__ twx) {
+                                                       int zp, int ndl, int p0, const int* __restrict__ perm,
+                                                       float scale, const float2* __restrict__ twx) {
   extern __shared__ float2 lds[];
   constexpr int K1 = N1 / 2, K2 = N2 / 2, NQ = N1 * N2;
   const int s = blockIdx.z, pl = blockIdx.y, z0 = blockIdx.x * zg;
@@ -145,7 +147,8 @@ __global__ __launch_bounds__(TFMM_BLOCK) void k_inv_xy(RhsPtrs P, const float2* 
     lds[q * zp + z] = Hb[e];
   }
   __syncthreads();
-  float2* __restrict__ Bb = P.b[s] + (long long)(p0 + pl) * ((long long)K1 * K2 * K3);
+  const int p = perm ? perm[p0 + pl] : p0 + pl;
+  float2* __restrict__ Bb = P.b[s] + (long long)p * ((long long)K1 * K2 * K3);
   xy_inverse<N1, N2, TFMM_BLOCK>(lds, Bb, K3, zg, zp, z0, scale, twx);
 }
 
@@ -166,7 +169,7 @@ static void xy_slab(int n1, int n2, int K3, int* zg, int* zp) {
 
 template <int N1>
 static bool dispatch_fwd_n2(int n2, const RhsPtrs& P, float2* H, int K3, int nrhs, int p0, int ndl,
-                            const float2* twx, hipStream_t st) {
+                            const int* perm, const float2* twx, hipStream_t st) {
   int zg, zp;
   switch (n2) {
 #define CASE2(N2)                                                                                      \
@@ -174,7 +177,7 @@ static bool dispatch_fwd_n2(int n2, const RhsPtrs& P, float2* H, int K3, int nrh
     xy_slab(N1, N2, K3, &zg, &zp);                                                                     \
     size_t lds = (size_t)N1 * N2 * zp * sizeof(float2);                                                \
     hipLaunchKernelGGL((k_fwd_xy<N1, N2>), dim3(K3 / zg, ndl, nrhs), dim3(TFMM_BLOCK), lds, st, P, H, K3, \
-                       zg, zp, ndl, p0, twx);                                                          \
+                       zg, zp, ndl, p0, perm, twx);                                                    \
     return true;                                                                                       \
   }
     TFMM_XY_SIZES(CASE2)
@@ -185,7 +188,7 @@ static bool dispatch_fwd_n2(int n2, const RhsPtrs& P, float2* H, int K3, int nrh
 
 template <int N1>
 static bool dispatch_inv_n2(int n2, const RhsPtrs& P, const float2* H, int K3, int nrhs, int p0, int ndl,
-                            float scale, const float2* twx, hipStream_t st) {
+                            const int* perm, float scale, const float2* twx, hipStream_t st) {
   int zg, zp;
   switch (n2) {
 #define CASE2(N2)                                                                                      \
@@ -193,7 +196,7 @@ static bool dispatch_inv_n2(int n2, const RhsPtrs& P, const float2* H, int K3, i
     xy_slab(N1, N2, K3, &zg, &zp);                                                                     \
     size_t lds = (size_t)N1 * N2 * zp * sizeof(float2);                                                \
     hipLaunchKernelGGL((k_inv_xy<N1, N2>), dim3(K3 / zg, ndl, nrhs), dim3(TFMM_BLOCK), lds, st, P, H, K3, \
-                       zg, zp, ndl, p0, scale, twx);                                                   \
+                       zg, zp, ndl, p0, perm, scale, twx);                                             \
     return true;                                                                                       \
   }
     TFMM_XY_SIZES(CASE2)
@@ -203,11 +206,11 @@ static bool dispatch_inv_n2(int n2, const RhsPtrs& P, const float2* H, int K3, i
 }
 
 hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const float2* twx, hipStream_t st, bool* supported) {
+                         const int* perm, const float2* twx, hipStream_t st, bool* supported) {
   bool ok = false;
   switch (n1) {
 #define CASE1(N1) \
-  case N1: ok = dispatch_fwd_n2<N1>(n2, P, H, K3, nrhs, p0, ndl, twx, st); break;
+  case N1: ok = dispatch_fwd_n2<N1>(n2, P, H, K3, nrhs, p0, ndl, perm, twx, st); break;
     TFMM_X_SIZES(CASE1)
 #undef CASE1
   }
@@ -216,16 +219,25 @@ hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, in
 }
 
 hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         float scale, const float2* twx, hipStream_t st, bool* supported) {
+                         const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported) {
   bool ok = false;
   switch (n1) {
 #define CASE1(N1) \
-  case N1: ok = dispatch_inv_n2<N1>(n2, P, H, K3, nrhs, p0, ndl, scale, twx, st); break;
+  case N1: ok = dispatch_inv_n2<N1>(n2, P, H, K3, nrhs, p0, ndl, perm, scale, twx, st); break;
     TFMM_X_SIZES(CASE1)
 #undef CASE1
   }
   *supported = ok;
   return ok ? hipGetLastError() : hipSuccess;
+}
+
+__global__ void k_zero(int* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_zero(int* p, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, st, p, n);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -29,7 +29,17 @@ struct ZArgs {
   int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
   int bf;                     // 1: split-BF16 (bf16x3) restoration, 0: FP32
   int tk2;                    // Tucker: 1 = register-chained restoration (tucker_restore.h)
+  // persistent launch: work items are taken from counter[0], counter[1]
+  // counts finished blocks (both zero between launches; the last block
+  // resets them); direction order perm[] (costliest first, NULL = identity)
+  const int* perm;
+  int* counter;
+  int ncu;                    // compute units of the device
 };
+
+// Dynamic LDS bytes a persistent launch adds past its working set (the
+// work-item broadcast slot).
+#define TFMM_LDS_SLOT 16
 
 // LDS bytes a restoration of a qt-pencil tile needs for a format / ranks /
 // chunk (host-side planning; qt = n1*n2 for the fused kernel).
@@ -47,10 +57,13 @@ struct RhsPtrs {
 
 // xy passes of the three-pass pipeline.  n1 in {8,...,64, 128, 256}, n2 <= 64;
 // twx = exp(-2 pi i m / n1), m < n1, is read only when n1 > 64.
+// Direction p0 + d of the launch is perm[p0 + d] (perm NULL: p0 + d).
 hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const float2* twx, hipStream_t st, bool* supported);
+                         const int* perm, const float2* twx, hipStream_t st, bool* supported);
 hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         float scale, const float2* twx, hipStream_t st, bool* supported);
+                         const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported);
+// Zero n ints (a kernel, so that it may be captured in a graph).
+hipError_t launch_zero(int* p, int n, hipStream_t st);
 hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported);
 
 // Fused single-kernel translation (one block per direction) for cubic grids

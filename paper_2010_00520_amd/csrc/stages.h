@@ -4,6 +4,11 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device_common.h"
 #include "launch.h"
 #include "tucker_restore.h"
@@ -361,31 +366,65 @@ __device__ __forceinline__ void zfft_rhs(const v4f (&acc)[T][CB], float2* H, lon
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2 of the three-pass pipeline: one block per (pencil tile, direction);
-// the restored tile is shared by every RHS of the launch.
+// Work items of the z-stage and fused kernels.  Block b starts with item b;
+// when the launch has more items than resident blocks (a.counter set), each
+// block then takes further items from counter[0] (offset by the grid size),
+// broadcast by thread 0 through the LDS slot past the working set.  A block
+// leaves once the items are exhausted; the last block to leave (counted in
+// counter[1]) resets both counters, so a launch, captured or not, needs no
+// clearing step.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int next_item(const ZArgs& a, float2* lds) {
+  if (!a.counter) return 0x7fffffff;
+  int* slot = reinterpret_cast<int*>(reinterpret_cast<char*>(lds) + a.lds_bytes);
+  if (threadIdx.x == 0) *slot = (int)gridDim.x + atomicAdd(a.counter, 1);
+  __syncthreads();
+  return *slot;
+}
+
+__device__ __forceinline__ void leave_queue(const ZArgs& a) {
+  if (a.counter && threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(a.counter + 1, 1) == (int)gridDim.x - 1) {
+      atomicExch(a.counter, 0);
+      atomicExch(a.counter + 1, 0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2 of the three-pass pipeline: a persistent grid walks the (direction,
+// pencil tile) items of the launch, costliest directions first; the restored
+// tile is shared by every RHS of the launch.
 // ---------------------------------------------------------------------------
 template <int FMT, int T, int CB, bool BF>
 __global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
   extern __shared__ float2 lds[];
   constexpr int NW = 4, QT = 16 * CB * NW;
   const int w = threadIdx.x >> 6;
-  const int q0 = blockIdx.x * QT;
-  const int pl = blockIdx.y, p = a.p0 + pl;
-  v4f acc[T][CB];
-  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
-  ZTwiddles<T> Z;
-  Z.load(a.roots);
-  for (int s = 0; s < a.nrhs; ++s) {
-    float2* Hs = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq);
-    zfft_rhs<T, CB>(acc, Hs, a.nq, 1, q0 + w * CB * 16, a.nq, Z);
+  const int ntile = a.nq / QT, nitems = ntile * a.ndl;
+  for (int it = blockIdx.x; it < nitems; it = next_item(a, lds)) {
+    const int pl = it / ntile, q0 = (it - pl * ntile) * QT;
+    const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
+    v4f acc[T][CB];
+    restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
+    ZTwiddles<T> Z;
+    Z.load(a.roots);
+    for (int s = 0; s < a.nrhs; ++s) {
+      float2* Hs = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq);
+      zfft_rhs<T, CB>(acc, Hs, a.nq, 1, q0 + w * CB * 16, a.nq, Z);
+    }
+    __syncthreads();
   }
+  leave_queue(a);
 }
 
 // ---------------------------------------------------------------------------
-// Fused translation for grids whose half spectrum fits in LDS: one block per
-// direction restores the whole T~_p into accumulators once, then for every RHS
-// runs the xy-FFTs, the z-stage and the inverse xy-FFTs on chip.  A and B are
-// the only device-memory traffic besides the stored operator.
+// Fused translation for grids whose half spectrum fits in LDS: a persistent
+// grid walks the directions (costliest first); per direction the block
+// restores the whole T~_p into accumulators once, then for every RHS runs the
+// xy-FFTs, the z-stage and the inverse xy-FFTs on chip.  A and B are the only
+// device-memory traffic besides the stored operator.
 // ---------------------------------------------------------------------------
 template <int FMT, int N, int NW, int CB, bool BF>
 __global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float scale) {
@@ -394,21 +433,39 @@ __global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float sca
   constexpr int ZP = (K & 1) ? K : K + 1;
   static_assert(NQ == 16 * CB * NW, "tile must cover every pencil");
   const int w = threadIdx.x >> 6;
-  const int p = a.p0 + blockIdx.x;
-  v4f acc[T][CB];
-  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, 0, lds);
-  ZTwiddles<T> Z;
-  Z.load(a.roots);
-  __syncthreads();
-  const long long blk = (long long)K * K * K;
-  for (int s = 0; s < a.nrhs; ++s) {
-    xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0, nullptr);
+  for (int it = blockIdx.x; it < a.ndl; it = next_item(a, lds)) {
+    const int p = a.perm ? a.perm[it] : it;
+    v4f acc[T][CB];
+    restore_tile<FMT, T, CB, NW, BF>(acc, a, p, 0, lds);
+    ZTwiddles<T> Z;
+    Z.load(a.roots);
     __syncthreads();
-    zfft_rhs<T, CB>(acc, lds, 1, ZP, w * CB * 16, NQ, Z);
-    __syncthreads();
-    xy_inverse<N, N, NT>(lds, P.b[s] + (long long)p * blk, K, K, ZP, 0, scale, nullptr);
-    __syncthreads();
+    const long long blk = (long long)K * K * K;
+    for (int s = 0; s < a.nrhs; ++s) {
+      xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0, nullptr);
+      __syncthreads();
+      zfft_rhs<T, CB>(acc, lds, 1, ZP, w * CB * 16, NQ, Z);
+      __syncthreads();
+      xy_inverse<N, N, NT>(lds, P.b[s] + (long long)p * blk, K, K, ZP, 0, scale, nullptr);
+      __syncthreads();
+    }
   }
+  leave_queue(a);
+}
+
+// Resident blocks per compute unit of a kernel at a dynamic LDS size (the
+// runtime query is cached: it costs host time on every launch otherwise).
+inline int resident_blocks(const void* fn, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<const void*, int, size_t>, int> cache;
+  const auto key = std::make_tuple(fn, threads, lds);
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds) != hipSuccess || n < 1) n = 1;
+  cache[key] = n;
+  return n;
 }
 
 // fused shape per grid: (waves, column blocks)
@@ -426,8 +483,12 @@ hipError_t run_zstage_p(const ZArgs& a, hipStream_t st) {
                               160 * 1024);
     attr = true;
   }
-  dim3 grid(a.nq / (64 * CB), a.ndl);
-  hipLaunchKernelGGL((k_zstage<FMT, T, CB, BF>), grid, dim3(256), (size_t)a.lds_bytes, st, a);
+  const size_t lds = (size_t)a.lds_bytes + TFMM_LDS_SLOT;
+  const int nitems = a.nq / (64 * CB) * a.ndl;
+  const int cap = a.ncu * resident_blocks((const void*)k_zstage<FMT, T, CB, BF>, 256, lds);
+  ZArgs b = a;
+  if (nitems <= cap) b.counter = nullptr;  // one item per block, no queue
+  hipLaunchKernelGGL((k_zstage<FMT, T, CB, BF>), dim3(std::min(nitems, cap)), dim3(256), lds, st, b);
   return hipGetLastError();
 }
 
@@ -448,7 +509,11 @@ hipError_t run_fused_p(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_
                               160 * 1024);
     attr = true;
   }
-  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB, BF>), dim3(a.ndl), dim3(64 * NW), (size_t)a.lds_bytes, st, a, P,
+  const size_t lds = (size_t)a.lds_bytes + TFMM_LDS_SLOT;
+  const int cap = a.ncu * resident_blocks((const void*)k_fused<FMT, N, NW, CB, BF>, 64 * NW, lds);
+  ZArgs b = a;
+  if (a.ndl <= cap) b.counter = nullptr;  // one direction per block, no queue
+  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB, BF>), dim3(std::min(a.ndl, cap)), dim3(64 * NW), lds, st, b, P,
                      scale);
   return hipGetLastError();
 }

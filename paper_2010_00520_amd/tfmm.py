@@ -105,6 +105,9 @@ SIGNATURES = [
     ("tfmm_set_profiling", _ST, [_VP, ctypes.c_int32]),
     ("tfmm_kernel_times", _ST, [_VP, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
                                 ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    ("tfmm_autotune", _ST, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                            ctypes.POINTER(ctypes.c_double)]),
+    ("tfmm_op_plan", _ST, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t]),
 ]
 
 _lib = None
@@ -175,6 +178,12 @@ class Operator:
         inf = OpInfo()
         _check(load().tfmm_op_info_get(self.handle, ctypes.byref(inf)))
         return inf.as_dict()
+
+    def plan(self) -> dict:
+        """Current tile plan: fused path, three-pass cb, register-chained restoration, tuned."""
+        v = (ctypes.c_int32 * 4)()
+        _check(load().tfmm_op_plan(self.handle, v, 4))
+        return {"fused": bool(v[0]), "cb": int(v[1]), "register_chained": bool(v[2]), "tuned": bool(v[3])}
 
     def ranks(self) -> np.ndarray:
         need = ctypes.c_size_t()
@@ -260,6 +269,14 @@ class Context:
         st, lat = ctypes.c_int(), ctypes.c_double()
         _check(load().tfmm_wait(self.handle, ticket, ctypes.byref(st), ctypes.byref(lat)))
         return st.value, lat.value
+
+    def autotune(self, op: "Operator", nrhs: int = 1, reps: int = 20):
+        """Time the admissible tile configurations for `nrhs` RHS and adopt the fastest.
+        Returns (plan dict, best median ms)."""
+        ch = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_double()
+        _check(load().tfmm_autotune(self.handle, op.handle, int(nrhs), int(reps), ch, ctypes.byref(ms)))
+        return {"fused": bool(ch[0]), "cb": int(ch[1]), "register_chained": bool(ch[2])}, ms.value
 
     def set_profiling(self, on: bool):
         _check(load().tfmm_set_profiling(self.handle, 1 if on else 0))

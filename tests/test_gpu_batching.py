@@ -1,0 +1,156 @@
+"""Batching on the GPU: persistent work-queue launches and captured hipGraphs.
+
+* A translation is captured on its first call for a given (operator, nrhs, A, B)
+  and replayed afterwards.  Replays, with the caller's own eager work and
+  synchronisations in between, must reproduce the eager result bit for bit,
+  also after A was rewritten in place.
+* The persistent kernels take their work items (direction, pencil tile) from an
+  atomic counter in cost order; the arithmetic of each item has a fixed order,
+  so a result must not depend on how RHS are batched into launches.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from factor_layout import random_factors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _ctx(no_graph):
+    """A context that never captures (eager reference) or always captures."""
+    import paper_2010_00520_amd as P
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    old = os.environ.get("TFMM_GRAPH")
+    os.environ["TFMM_GRAPH"] = "0" if no_graph else "1"
+    try:
+        return P.Context(0)
+    finally:
+        if old is None:
+            os.environ.pop("TFMM_GRAPH", None)
+        else:
+            os.environ["TFMM_GRAPH"] = old
+
+
+CASES = [
+    ("tucker3d", (16, 16, 16), "fp32"),   # fused kernel
+    ("tucker3d", (16, 16, 16), "bf16x3"),
+    ("tt3d", (8, 12, 4), "fp32"),         # three-pass pipeline
+    ("htucker4d", (24, 8, 8), "fp32"),    # three-pass with the per-call core contraction
+]
+
+
+def _factors(fmt, K, L):
+    n = tuple(2 * k for k in K)
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(4321)
+    ranks = {"htucker4d": (6, 5, 4, 7, 10, 9)}.get(fmt)
+    return ndir, random_factors(fmt, n, ndir, rng, ranks)
+
+
+@pytest.mark.parametrize("fmt,K,prec", CASES)
+def test_graph_replays_match_eager(fmt, K, prec):
+    L = 4
+    ndir, (rk, data, comp) = _factors(fmt, K, L)
+    A_np = synth.gaussian_patterns((2, ndir) + K, 31)
+    A2_np = synth.gaussian_patterns((2, ndir) + K, 32)
+
+    eager = _ctx(no_graph=True)
+    op_e = eager.import_factors(K, L, fmt, rk, data, prec=prec)
+    A = torch.from_numpy(A_np).cuda()
+    A2 = torch.from_numpy(A2_np).cuda()
+    Be, Be2 = torch.zeros_like(A), torch.zeros_like(A)
+    eager.translate(op_e, A, Be)
+    eager.translate(op_e, A2, Be2)
+    torch.cuda.synchronize()
+    ref, ref2 = Be.cpu(), Be2.cpu()
+    op_e.release()
+    eager.close()
+
+    ctx = _ctx(no_graph=False)
+    op = ctx.import_factors(K, L, fmt, rk, data, prec=prec)
+    Ad = A.clone()
+    B = torch.zeros_like(A)
+    for it in range(4):  # call 0 runs eagerly and captures; 1..3 replay the graph
+        B.zero_()
+        ctx.translate(op, Ad, B)
+        junk = (Ad * 2).sum()  # the caller's own eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(B.cpu(), ref), f"replay {it} differs from the eager result"
+        del junk
+    Ad.copy_(A2)  # same buffer, new content: the replay must read it
+    for it in range(2):
+        B.zero_()
+        ctx.translate(op, Ad, B)
+        torch.cuda.synchronize()
+        assert torch.equal(B.cpu(), ref2), f"replay {it} after rewriting A differs"
+    # and the numbers are the method's: compare with the oracle
+    assert O.rel_l2(B.cpu().numpy().astype(np.complex128), O.translate_compressed(A2_np, comp)) < (
+        1e-4 if prec == "bf16x3" else 2e-5)
+    op.release()
+    ctx.close()
+
+
+@pytest.mark.parametrize("fmt,K,prec", CASES[:1] + CASES[2:3])
+def test_result_independent_of_rhs_batching(fmt, K, prec):
+    """Three RHS in one launch equal three single-RHS launches bit for bit."""
+    L = 4
+    ndir, (rk, data, comp) = _factors(fmt, K, L)
+    A = torch.from_numpy(synth.gaussian_patterns((3, ndir) + K, 33)).cuda()
+    ctx = _ctx(no_graph=False)
+    op = ctx.import_factors(K, L, fmt, rk, data, prec=prec)
+    B = torch.zeros_like(A)
+    ctx.translate(op, A, B)
+    Bs = torch.zeros_like(A)
+    for s in range(3):
+        ctx.translate(op, A[s:s + 1].contiguous(), Bs[s:s + 1])
+    torch.cuda.synchronize()
+    assert torch.equal(B.cpu(), Bs.cpu())
+    op.release()
+    ctx.close()
+
+
+@pytest.mark.parametrize("fmt,K", [("tt3d", (8, 12, 4)), ("tucker3d", (8, 8, 8))])
+def test_autotune_adopts_a_plan_and_stays_correct(fmt, K, tmp_path):
+    """The autotuner times every admissible tile configuration, adopts the fastest,
+    records it in the cache file, and a new context picks the choice up."""
+    L = 4
+    ndir, (rk, data, comp) = _factors(fmt, K, L)
+    cache = tmp_path / "tune.txt"
+    os.environ["TFMM_TUNE_CACHE"] = str(cache)
+    try:
+        ctx = _ctx(no_graph=True)
+        op = ctx.import_factors(K, L, fmt, rk, data)
+        plan, ms = ctx.autotune(op, nrhs=2, reps=3)
+        assert ms > 0
+        p = op.plan()
+        assert p["tuned"] and p["fused"] == plan["fused"] and p["cb"] == plan["cb"]
+        A_np = synth.gaussian_patterns((2, ndir) + K, 34)
+        A = torch.from_numpy(A_np).cuda()
+        B = torch.zeros_like(A)
+        ctx.translate(op, A, B)
+        torch.cuda.synchronize()
+        assert O.rel_l2(B.cpu().numpy().astype(np.complex128), O.translate_compressed(A_np, comp)) < 2e-5
+        op.release()
+        ctx.close()
+        assert cache.read_text().count("fused=") == 1
+        ctx2 = _ctx(no_graph=True)  # reads the cache file
+        op2 = ctx2.import_factors(K, L, fmt, rk, data)
+        assert not op2.plan()["tuned"]
+        B2 = torch.zeros_like(A)
+        ctx2.translate(op2, A, B2)  # same key (nrhs bucket 2-4): the cached choice applies
+        torch.cuda.synchronize()
+        p2 = op2.plan()
+        assert p2["tuned"] and p2["fused"] == plan["fused"] and p2["cb"] == plan["cb"]
+        assert torch.equal(B.cpu(), B2.cpu())
+        op2.release()
+        ctx2.close()
+    finally:
+        os.environ.pop("TFMM_TUNE_CACHE", None)
