@@ -366,6 +366,82 @@ __device__ __forceinline__ void zfft_rhs(const v4f (&acc)[T][CB], float2* H, lon
 }
 
 // ---------------------------------------------------------------------------
+// z-stage of the fused 32^3 kernel with whole pencils per lane.  After the
+// restoration, each wave moves its 128 accumulator columns through LDS so that
+// lane l holds all 32 frequencies of pencils l and 64 + l of the wave.  Per RHS
+// a lane then transforms its pencils alone, splitting the pruned 32-point
+// transform (16 nonzero inputs) into even and odd outputs:
+//   X[2m]   = DFT16(x)[m],        X[2m+1] = DFT16(x[z] w^z)[m],
+//   y[z']   = IDFT16(P_even)[z'] + w^-z' IDFT16(P_odd)[z'],   z' < 16,
+// with w = exp(-2 pi i / 32); the 1/N scale is applied by the xy stage.
+// ---------------------------------------------------------------------------
+__device__ constexpr float kW32[16][2] = {
+    {0x1.0000000000000p+0f, 0.0f},
+    {0x1.f6297c0000000p-1f, -0x1.8f8b840000000p-3f},
+    {0x1.d906bc0000000p-1f, -0x1.87de2a0000000p-2f},
+    {0x1.a9b6620000000p-1f, -0x1.1c73b40000000p-1f},
+    {0x1.6a09e60000000p-1f, -0x1.6a09e60000000p-1f},
+    {0x1.1c73b40000000p-1f, -0x1.a9b6620000000p-1f},
+    {0x1.87de2a0000000p-2f, -0x1.d906bc0000000p-1f},
+    {0x1.8f8b840000000p-3f, -0x1.f6297c0000000p-1f},
+    {0.0f, -0x1.0000000000000p+0f},
+    {-0x1.8f8b840000000p-3f, -0x1.f6297c0000000p-1f},
+    {-0x1.87de2a0000000p-2f, -0x1.d906bc0000000p-1f},
+    {-0x1.1c73b40000000p-1f, -0x1.a9b6620000000p-1f},
+    {-0x1.6a09e60000000p-1f, -0x1.6a09e60000000p-1f},
+    {-0x1.a9b6620000000p-1f, -0x1.1c73b40000000p-1f},
+    {-0x1.d906bc0000000p-1f, -0x1.87de2a0000000p-2f},
+    {-0x1.f6297c0000000p-1f, -0x1.8f8b840000000p-3f}};
+
+template <int CB>
+__device__ __forceinline__ void acc_to_pencils32(const v4f (&acc)[4][CB], float2 (&tz)[CB / 4][32], float2* lds) {
+  static_assert(CB % 4 == 0, "whole pencils per lane need 64 columns per round");
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, j = l & 15;
+  float2* reg = lds + w * (64 * 33);
+#pragma unroll
+  for (int r = 0; r < CB / 4; ++r) {
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          reg[(cc * 16 + j) * 33 + 8 * t + 2 * g + e] =
+              make_float2(acc[t][4 * r + cc][2 * e], acc[t][4 * r + cc][2 * e + 1]);
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 32; ++f) tz[r][f] = reg[l * 33 + f];
+    __syncthreads();
+  }
+}
+
+// H: the wave's half-spectrum slab, element (z, pencil q) at q*ZP + z.
+template <int NP, int ZP>
+__device__ __forceinline__ void zfft_pencils32(const float2 (&tz)[NP][32], float2* H, int qbase) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int u = 0; u < NP; ++u) {
+    float2* h = H + (qbase + 64 * u + l) * ZP;
+    float2 x[16], xo[16], E[16];
+#pragma unroll
+    for (int z = 0; z < 16; ++z) {
+      x[z] = h[z];
+      xo[z] = cmul(x[z], make_float2(kW32[z][0], kW32[z][1]));
+    }
+    dft_full_fwd_16(x, E);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) E[m] = cmul(E[m], tz[u][2 * m]);
+    dft_full_inv_16(E, x);  // x <- even part of the output
+    dft_full_fwd_16(xo, E);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) E[m] = cmul(E[m], tz[u][2 * m + 1]);
+    dft_full_inv_16(E, xo);
+#pragma unroll
+    for (int z = 0; z < 16; ++z) h[z] = cadd(x[z], cmulconj(xo[z], make_float2(kW32[z][0], kW32[z][1])));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Work items of the z-stage and fused kernels.  Block b starts with item b;
 // when the launch has more items than resident blocks (a.counter set), each
 // block then takes further items from counter[0] (offset by the grid size),
@@ -398,49 +474,70 @@ __device__ __forceinline__ void leave_queue(const ZArgs& a) {
 // tile is shared by every RHS of the launch.
 // ---------------------------------------------------------------------------
 template <int FMT, int T, int CB, bool BF>
-__global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void zstage_item(const ZArgs& a, int it, float2* lds) {
   constexpr int NW = 4, QT = 16 * CB * NW;
   const int w = threadIdx.x >> 6;
-  const int ntile = a.nq / QT, nitems = ntile * a.ndl;
-  for (int it = blockIdx.x; it < nitems; it = next_item(a, lds)) {
-    const int pl = it / ntile, q0 = (it - pl * ntile) * QT;
-    const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
-    v4f acc[T][CB];
-    restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
-    ZTwiddles<T> Z;
-    Z.load(a.roots);
-    for (int s = 0; s < a.nrhs; ++s) {
-      float2* Hs = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq);
-      zfft_rhs<T, CB>(acc, Hs, a.nq, 1, q0 + w * CB * 16, a.nq, Z);
-    }
-    __syncthreads();
+  const int ntile = a.nq / QT;
+  const int pl = it / ntile, q0 = (it - pl * ntile) * QT;
+  const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
+  v4f acc[T][CB];
+  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
+  ZTwiddles<T> Z;
+  Z.load(a.roots);
+  for (int s = 0; s < a.nrhs; ++s) {
+    float2* Hs = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq);
+    zfft_rhs<T, CB>(acc, Hs, a.nq, 1, q0 + w * CB * 16, a.nq, Z);
   }
-  leave_queue(a);
+  __syncthreads();
+}
+
+// The first item of every block is its own index; only a launch with more
+// items than resident blocks enters the queue loop (a separate copy of the
+// item body, so the common single-item path carries no loop state).
+template <int FMT, int T, int CB, bool BF>
+__global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
+  extern __shared__ float2 lds[];
+  constexpr int QT = 16 * CB * 4;
+  const int nitems = a.nq / QT * a.ndl;
+  zstage_item<FMT, T, CB, BF>(a, blockIdx.x, lds);
+  if (a.counter) {
+    for (int it = next_item(a, lds); it < nitems; it = next_item(a, lds)) zstage_item<FMT, T, CB, BF>(a, it, lds);
+    leave_queue(a);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Fused translation for grids whose half spectrum fits in LDS: a persistent
-// grid walks the directions (costliest first); per direction the block
-// restores the whole T~_p into accumulators once, then for every RHS runs the
-// xy-FFTs, the z-stage and the inverse xy-FFTs on chip.  A and B are the only
-// device-memory traffic besides the stored operator.
+// Fused translation for grids whose half spectrum fits in LDS: per direction
+// a block restores the whole T~_p into accumulators once, then for every RHS
+// runs the xy-FFTs, the z-stage and the inverse xy-FFTs on chip.  A and B are
+// the only device-memory traffic besides the stored operator.
 // ---------------------------------------------------------------------------
 template <int FMT, int N, int NW, int CB, bool BF>
-__global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float scale) {
-  extern __shared__ float2 lds[];
+__device__ __forceinline__ void fused_item(const ZArgs& a, const RhsPtrs& P, float scale, int it, float2* lds) {
   constexpr int T = N / 8, K = N / 2, NQ = N * N, NT = 64 * NW;
   constexpr int ZP = (K & 1) ? K : K + 1;
   static_assert(NQ == 16 * CB * NW, "tile must cover every pencil");
   const int w = threadIdx.x >> 6;
-  for (int it = blockIdx.x; it < a.ndl; it = next_item(a, lds)) {
-    const int p = a.perm ? a.perm[it] : it;
-    v4f acc[T][CB];
-    restore_tile<FMT, T, CB, NW, BF>(acc, a, p, 0, lds);
+  const int p = a.perm ? a.perm[it] : it;
+  v4f acc[T][CB];
+  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, 0, lds);
+  const long long blk = (long long)K * K * K;
+  if constexpr (N == 32 && CB % 4 == 0) {
+    float2 tz[CB / 4][32];
+    __syncthreads();
+    acc_to_pencils32<CB>(acc, tz, lds);
+    for (int s = 0; s < a.nrhs; ++s) {
+      xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0, nullptr);
+      __syncthreads();
+      zfft_pencils32<CB / 4, ZP>(tz, lds, w * CB * 16);
+      __syncthreads();
+      xy_inverse<N, N, NT>(lds, P.b[s] + (long long)p * blk, K, K, ZP, 0, scale, nullptr);
+      __syncthreads();
+    }
+  } else {
     ZTwiddles<T> Z;
     Z.load(a.roots);
     __syncthreads();
-    const long long blk = (long long)K * K * K;
     for (int s = 0; s < a.nrhs; ++s) {
       xy_forward<N, N, NT>(lds, P.a[s] + (long long)p * blk, K, K, ZP, 0, nullptr);
       __syncthreads();
@@ -450,7 +547,16 @@ __global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float sca
       __syncthreads();
     }
   }
-  leave_queue(a);
+}
+
+// One block per direction, blocks numbered in cost order: the hardware
+// dispatcher hands directions to compute units as they free up, i.e. it is
+// the work queue.  (A queue loop inside this kernel keeps its restoration
+// state live across items and spills the 256 registers a wave has here.)
+template <int FMT, int N, int NW, int CB, bool BF>
+__global__ __launch_bounds__(64 * NW) void k_fused(ZArgs a, RhsPtrs P, float scale) {
+  extern __shared__ float2 lds[];
+  fused_item<FMT, N, NW, CB, BF>(a, P, scale, blockIdx.x, lds);
 }
 
 // Resident blocks per compute unit of a kernel at a dynamic LDS size (the
@@ -509,11 +615,7 @@ hipError_t run_fused_p(const ZArgs& a, const RhsPtrs& P, float scale, hipStream_
                               160 * 1024);
     attr = true;
   }
-  const size_t lds = (size_t)a.lds_bytes + TFMM_LDS_SLOT;
-  const int cap = a.ncu * resident_blocks((const void*)k_fused<FMT, N, NW, CB, BF>, 64 * NW, lds);
-  ZArgs b = a;
-  if (a.ndl <= cap) b.counter = nullptr;  // one direction per block, no queue
-  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB, BF>), dim3(std::min(a.ndl, cap)), dim3(64 * NW), lds, st, b, P,
+  hipLaunchKernelGGL((k_fused<FMT, N, NW, CB, BF>), dim3(a.ndl), dim3(64 * NW), (size_t)a.lds_bytes, st, a, P,
                      scale);
   return hipGetLastError();
 }
