@@ -121,9 +121,10 @@ def time_steps(ctx, op, A, B, steps, warmup, torch):
     return (t1 - t0) / steps * 1e3, lat, kt
 
 
-def cpu_baseline(w, fmt, gpu_B, A_np, target_s):
+def cpu_baseline(w, fmt, gpu_Bs, A_np, target_s):
     """The FP64 oracle on a bounded sample of directions: restoration + FFT convolution timed
-    on the host; also the reference the GPU result is checked against on that sample."""
+    on the host; also the reference each GPU result (one per precision) is checked against
+    on that sample: relative L2 error per direction, max and median."""
     import oracle as O
 
     try:
@@ -136,7 +137,8 @@ def cpu_baseline(w, fmt, gpu_B, A_np, target_s):
     # grow the sample until it costs about target_s seconds
     sample = []
     t_total = 0.0
-    errs, errs_exact = [], []
+    errs = {p: [] for p in gpu_Bs}
+    errs_exact = []
     order = rng.permutation(ndir)
     ctxm = threadpool_limits(limits=1) if threadpool_limits else None
     try:
@@ -149,7 +151,8 @@ def cpu_baseline(w, fmt, gpu_B, A_np, target_s):
             Bc = O.translate_compressed(Ap, comp)
             t_total += time.perf_counter() - t0
             Bex = O.translate_fft(Ap, Th)
-            errs.append(O.rel_l2(gpu_B[:, p:p + 1], Bex))
+            for prec, gB in gpu_Bs.items():
+                errs[prec].append(O.rel_l2(gB[:, p:p + 1], Bex))
             errs_exact.append(O.rel_l2(Bc, Bex))
             sample.append(int(p))
             if t_total >= target_s or len(sample) >= ndir:
@@ -166,8 +169,8 @@ def cpu_baseline(w, fmt, gpu_B, A_np, target_s):
         "sample": f"{len(sample)} of {ndir} directions x {A_np.shape[0]} RHS of the {w.name} workload "
                   f"({fmt} restore + FFT convolution, FP64 numpy, 1 thread); {t_total:.1f} s",
         "cpu": platform.processor() or platform.machine(),
-        "gpu_rel_err_max": float(max(errs)),
-        "gpu_rel_err_median": float(np.median(errs)),
+        "gpu_rel_err_max": {p: float(max(e)) for p, e in errs.items()},
+        "gpu_rel_err_median": {p: float(np.median(e)) for p, e in errs.items()},
         "oracle_compressed_rel_err_max": float(max(errs_exact)),
     }
 
@@ -285,7 +288,9 @@ def main():
 
     w = workload(args.workload)
     fmt = args.fmt or w.fmt
-    prec = args.prec or w.precision
+    # the compressed path is timed in both restoration arithmetics; the headline
+    # is split-BF16 (bf16x3, FP32 accumulation), FP32 is reported beside it
+    precs = [args.prec] if args.prec else ["bf16x3", "fp32"]
     A_np = synth.patterns_for(w)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
@@ -297,68 +302,71 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     A = torch.from_numpy(A_np).to(dev)
-    B = torch.zeros_like(A)
-    Bf = torch.zeros_like(A)
-    out = {}
+    res = {}
     with P.Context(0) as ctx:
-        t0 = time.perf_counter()
-        op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
-        setup_s = time.perf_counter() - t0
+        for prec in precs:
+            B = torch.zeros_like(A)
+            t0 = time.perf_counter()
+            op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
+            setup_s = time.perf_counter() - t0
+            ms, lat, kt = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
+            res[prec] = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": op.ranks(), "setup_s": setup_s,
+                         "plan": op.plan(), "B": B.cpu().numpy().astype(np.complex128)}
+            op.release()
         full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
-        info, finfo = op.info(), full.info()
-        ranks = op.ranks()
-        ms, lat, kt = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
+        Bf = torch.zeros_like(A)
         ms_f, lat_f, kt_f = time_steps(ctx, full, A, Bf, args.steps, args.warmup, torch)
-        gpu_B = B.cpu().numpy().astype(np.complex128)
-        gpu_Bf = Bf.cpu().numpy().astype(np.complex128)
-        op.release()
+        finfo = full.info()
         full.release()
 
     ndir, nrhs = w.n_dir, w.nrhs
     units = w.boxes * ndir * nrhs
-    value = units / (ms * 1e-3)
-    value_f = units / (ms_f * 1e-3)
     n = w.n
-    # roofline of the dominant kernel of the compressed path (largest total time)
-    zname = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches"])
     prof_steps = min(args.steps, 100)
-    zms = kt[zname]["avg_ms"] * kt[zname]["launches"] / prof_steps  # per step
-    flops = restore_flops(fmt, ranks, n, ndir)
-    stored = info["bytes_stored"]
-    io = 2 * 8 * units  # A read + B written, complex64
-    # the fused kernel moves A and B as well; the three-pass z-stage only reads the operator
-    alg_bytes = stored + (io if zname.startswith("fused") else 0)
-    valu_flops = fft_flops(w.K, n, ndir, nrhs) if zname.startswith("fused") else 0.0
-    mfma_tfs = flops / (zms * 1e-3) / 1e12
-    hbm_gbs = alg_bytes / (zms * 1e-3) / 1e9
-    if prec == "bf16x3":
-        # each FP32 product is three bf16 products (hi*hi + hi*lo + lo*hi) on the bf16 matrix cores
-        cand = [("mfma", 3 * mfma_tfs, PEAK_BF16_MFMA_TFLOPS, "TFLOP/s")]
-    else:
-        cand = [("mfma", mfma_tfs, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s")]
-    cand.append(("hbm", hbm_gbs, PEAK_HBM_GBS, "GB/s"))
-    if valu_flops:
-        cand.append(("alu", valu_flops / (zms * 1e-3) / 1e12, PEAK_FP32_VALU_TFLOPS, "TFLOP/s"))
-    bound = max(cand, key=lambda c: c[1] / c[2])
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        try:
-            tr = json.load(open(tpath))
-            key = f"{args.workload}:{fmt}:{zname}"
-            if key in tr and tr[key].get("kernel_sha") == _kernel_sha():
-                traffic = tr[key]["bytes_per_launch"]
-        except Exception:
-            traffic = None
-    roof = {"bound": bound[0], "achieved": round(bound[1], 3), "peak": bound[2], "unit": bound[3],
-            "frac": round(bound[1] / bound[2], 4), "traffic": traffic, "kernel": zname,
-            "kernel_avg_ms": zms, "algorithmic_flops": flops, "algorithmic_bytes": alg_bytes,
-            "fft_flops": valu_flops,
-            "other_bound": {c[0]: {"achieved": round(c[1], 3), "peak": c[2], "unit": c[3],
-                                   "frac": round(c[1] / c[2], 4)} for c in cand if c[0] != bound[0]}}
+
+    def roofline(prec, r):
+        kt, info = r["kt"], r["info"]
+        # dominant kernel of the compressed path (largest total time)
+        zname = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches"])
+        zms = kt[zname]["avg_ms"] * kt[zname]["launches"] / prof_steps  # per step
+        flops = restore_flops(fmt, r["ranks"], n, ndir)
+        io = 2 * 8 * units  # A read + B written, complex64
+        # the fused kernel moves A and B as well; the three-pass z-stage only reads the operator
+        alg_bytes = info["bytes_stored"] + (io if zname.startswith("fused") else 0)
+        valu_flops = fft_flops(w.K, n, ndir, nrhs) if zname.startswith("fused") else 0.0
+        mfma_tfs = flops / (zms * 1e-3) / 1e12
+        if prec == "bf16x3":
+            # each FP32 product is three bf16 products (hi*hi + hi*lo + lo*hi) on the bf16 matrix cores
+            cand = [("mfma", 3 * mfma_tfs, PEAK_BF16_MFMA_TFLOPS, "TFLOP/s")]
+        else:
+            cand = [("mfma", mfma_tfs, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s")]
+        cand.append(("hbm", alg_bytes / (zms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"))
+        if valu_flops:
+            cand.append(("alu", valu_flops / (zms * 1e-3) / 1e12, PEAK_FP32_VALU_TFLOPS, "TFLOP/s"))
+        bound = max(cand, key=lambda c: c[1] / c[2])
+        traffic = None
+        tpath = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tpath):
+            try:
+                tr = json.load(open(tpath))
+                key = f"{args.workload}:{fmt}:{prec}:{zname}"
+                if key in tr and tr[key].get("kernel_sha") == _kernel_sha():
+                    traffic = tr[key]["bytes_per_launch"]
+            except Exception:
+                traffic = None
+        return {"bound": bound[0], "achieved": round(bound[1], 3), "peak": bound[2], "unit": bound[3],
+                "frac": round(bound[1] / bound[2], 4), "traffic": traffic, "kernel": zname,
+                "kernel_avg_ms": zms, "algorithmic_flops": flops, "algorithmic_bytes": alg_bytes,
+                "fft_flops": valu_flops,
+                "other_bound": {c[0]: {"achieved": round(c[1], 3), "peak": c[2], "unit": c[3],
+                                       "frac": round(c[1] / c[2], 4)} for c in cand if c[0] != bound[0]}}
+
+    head = precs[0]
+    r = res[head]
+    ms = r["ms"]
     out = {
         "metric": "translated grid-pts*dirs/s, compressed operator (vs uncompressed), rel err <= 1e-4",
-        "value": value,
+        "value": units / (ms * 1e-3),
         "unit": "grid-pts*dirs/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -367,26 +375,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "bf16x3 (f32 accumulate)",
+        "dtype": "f32" if head == "fp32" else "bf16x3 (split-bf16 MFMA, f32 accumulate; FFTs f32)",
         "data": "synthetic",
         "config": {"workload": w.name, "K": list(w.K), "box": w.box, "L": w.L, "n_dir": ndir, "fmt": fmt,
-                   "tol": w.tol, "nrhs": nrhs, "precision": prec},
-        "p50_ms": float(np.percentile(lat, 50)),
-        "p99_ms": float(np.percentile(lat, 99)),
-        "uncompressed": {"value": value_f, "ms_per_step": ms_f, "p50_ms": float(np.percentile(lat_f, 50)),
-                         "p99_ms": float(np.percentile(lat_f, 99)), "kernels": kt_f},
+                   "tol": w.tol, "nrhs": nrhs, "precision": head},
+        "p50_ms": float(np.percentile(r["lat"], 50)),
+        "p99_ms": float(np.percentile(r["lat"], 99)),
+        "uncompressed": {"value": units / (ms_f * 1e-3), "ms_per_step": ms_f,
+                         "p50_ms": float(np.percentile(lat_f, 50)), "p99_ms": float(np.percentile(lat_f, 99)),
+                         "kernels": kt_f},
         "time_ratio_compressed_over_full": ms / ms_f,
-        "memory_fraction": info["bytes_stored"] / finfo["bytes_stored"],
-        "op": {"ranks_max": info["ranks"], "rel_err_fro": info["rel_err_fro"], "setup_s": setup_s,
-               "bytes_stored": info["bytes_stored"], "bytes_full": finfo["bytes_stored"]},
-        "kernels": kt,
+        "memory_fraction": r["info"]["bytes_stored"] / finfo["bytes_stored"],
+        "op": {"ranks_max": r["info"]["ranks"], "rel_err_fro": r["info"]["rel_err_fro"], "setup_s": r["setup_s"],
+               "bytes_stored": r["info"]["bytes_stored"], "bytes_full": finfo["bytes_stored"], "plan": r["plan"]},
+        "kernels": r["kt"],
         "fft_flops_per_step": fft_flops(w.K, n, ndir, nrhs),
-        "roofline": roof,
+        "roofline": roofline(head, r),
         "cpu_baseline": None,
     }
+    for prec in precs[1:]:
+        q = res[prec]
+        out[prec] = {"value": units / (q["ms"] * 1e-3), "ms_per_step": q["ms"],
+                     "p50_ms": float(np.percentile(q["lat"], 50)), "p99_ms": float(np.percentile(q["lat"], 99)),
+                     "time_ratio_compressed_over_full": q["ms"] / ms_f, "kernels": q["kt"],
+                     "roofline": roofline(prec, q)}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, fmt, gpu_B, A_np, args.cpu_seconds)
-        out["rel_err_vs_fp64"] = out["cpu_baseline"]["gpu_rel_err_max"]
+        out["cpu_baseline"] = cpu_baseline(w, fmt, {p: res[p]["B"] for p in precs}, A_np, args.cpu_seconds)
+        out["rel_err_vs_fp64"] = out["cpu_baseline"]["gpu_rel_err_max"][head]
     print(json.dumps(out))
 
 
@@ -394,8 +409,8 @@ def _kernel_sha():
     import hashlib
 
     h = hashlib.sha256()
-    for f in ("device_common.h", "gen_dft.py", "kernels.hip", "stages.h", "xy_stages.h", "zstage_full.hip",
-              "zstage_tt3d.hip", "zstage_tt4d.hip", "zstage_tucker.hip"):
+    for f in ("device_common.h", "gen_dft.py", "kernels.hip", "stages.h", "tucker_restore.h", "xy_stages.h",
+              "zstage_full.hip", "zstage_tt3d.hip", "zstage_tt4d.hip", "zstage_tucker.hip"):
         with open(os.path.join(ROOT, "paper_2010_00520_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -248,20 +248,27 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
   constexpr int PART = PF * NT, VP = (8 * N3 + NT - 1) / NT;
   const int nparts = (csz + PART - 1) / PART;
   float px[PF], py[PF], vx[VP], vy[VP];
+  // The element indices of a part do not change between chunks; `to` is made
+  // opaque so the index arithmetic is redone per chunk rather than hoisted out
+  // of the chunk loop into registers (which would spill).
   auto load_part = [&](int P, int c0) {
     const int kc = min(8, r3 - c0);
+    int to = tid;
+    asm volatile("" : "+v"(to));
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int e = P * PART + tid + u * NT;
+      const int e = P * PART + to + u * NT;
       const float2 v = e < csz ? src.at(e, c0, kc) : make_float2(0.f, 0.f);
       px[u] = v.x;
       py[u] = v.y;
     }
   };
   auto store_part = [&](int P) {
+    int to = tid;
+    asm volatile("" : "+v"(to));
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
-      const int e = P * PART + tid + u * NT;
+      const int e = P * PART + to + u * NT;
       if (e < csz) stage<BF>(sC, src.lds_index(e, s1), make_float2(px[u], py[u]));
     }
   };
@@ -297,6 +304,11 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
   for (int h = 0; h < nch; ++h) {
     const int c0 = 8 * h;
     const bool more = h + 1 < nch;
+    // lane indices made opaque per chunk (see load_part): fragment addresses
+    // are recomputed rather than kept live across the chunk loop
+    int lo = tid & 63;
+    asm volatile("" : "+v"(lo));
+    const int kg = lo >> 4, i = lo & 15, j = lo & 15;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const int fz = 8 * t + (i >> 1), ri = i & 1;
