@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--fmt", default=None, help="override the compressed format")
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
                     help="override the restoration arithmetic")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run tfmm_autotune for the workload's RHS count before timing")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -376,9 +378,10 @@ def main():
             t0 = time.perf_counter()
             op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
             setup_s = time.perf_counter() - t0
+            tuned = ctx.autotune(op, nrhs=w.nrhs, reps=10) if args.autotune else None
             ms, lat, kt = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
             res[prec] = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": op.ranks(), "setup_s": setup_s,
-                         "plan": op.plan(), "B": B.cpu().numpy().astype(np.complex128)}
+                         "plan": op.plan(), "autotune": tuned, "B": B.cpu().numpy().astype(np.complex128)}
             op.release()
         full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
         Bf = torch.zeros_like(A)
@@ -454,7 +457,8 @@ def main():
         "time_ratio_compressed_over_full": ms / ms_f,
         "memory_fraction": r["info"]["bytes_stored"] / finfo["bytes_stored"],
         "op": {"ranks_max": r["info"]["ranks"], "rel_err_fro": r["info"]["rel_err_fro"], "setup_s": r["setup_s"],
-               "bytes_stored": r["info"]["bytes_stored"], "bytes_full": finfo["bytes_stored"], "plan": r["plan"]},
+               "bytes_stored": r["info"]["bytes_stored"], "bytes_full": finfo["bytes_stored"], "plan": r["plan"],
+               "autotune": r["autotune"]},
         "kernels": r["kt"],
         "fft_flops_per_step": fft_flops(w.K, n, ndir, nrhs),
         "roofline": roofline(head, r),
