@@ -37,13 +37,17 @@ struct Cx<false> {
   static constexpr int KS = 2;  // complex k per K-step
   typedef float A;
   typedef float B;
-  // p: the k-contiguous row at the step's first k.  A is real-embedded (row ri).
+  // p: the k-contiguous row at the step's first k.  A is real-embedded (row
+  // ri): re for ri == ki, im otherwise, negated for (ri, ki) = (0, 1); one
+  // 32-bit load and a sign flip.
   static __device__ __forceinline__ A load_a(const float2* p, int kg, int ri) {
-    return embed_a(p[kg >> 1], ri, kg & 1);
+    const float* f = reinterpret_cast<const float*>(p);
+    const unsigned neg = (ri == 0 && (kg & 1)) ? 0x80000000u : 0u;
+    return __uint_as_float(__float_as_uint(f[2 * (kg >> 1) + (ri ^ (kg & 1))]) ^ neg);
   }
+  // stacked operand: component kg % 2 of complex kg / 2, i.e. float kg
   static __device__ __forceinline__ B load_b(const float2* p, int kg) {
-    const float2 v = p[kg >> 1];
-    return (kg & 1) ? v.y : v.x;
+    return reinterpret_cast<const float*>(p)[kg];
   }
   static __device__ __forceinline__ B zero_b() { return 0.f; }
   static __device__ __forceinline__ v4f mma(A a, B b, v4f c) { return mfma4(a, b, c); }
@@ -98,7 +102,8 @@ __host__ __device__ __forceinline__ int tk_stride(int r) {
 __host__ __device__ __forceinline__ int tk_align4(int e) { return (e + 3) & ~3; }
 
 // LDS layout (complex elements) of the Tucker restoration of a tile with nfx
-// x-rows: U1 rows, U2, U3 columns of the chunk (pair), C chunk, W1 chunk.
+// x-rows: U1 (FP32: embedded, two rows per x-row), U2, U3 columns of the
+// chunk, C chunk (rows padded to an even number of b), W1 chunk.
 struct TuckerLds {
   int s1, s2, fs, oU1, oU2, oV, oC, oW1, total;
   template <bool BF>
@@ -107,10 +112,10 @@ struct TuckerLds {
     s2 = tk_stride<BF>(r2);
     fs = 8 * s2 + 2;  // W1 x-row stride, skewed against the 16 x-rows of a GEMM tile
     oU1 = 0;
-    oU2 = tk_align4(oU1 + nfx * s1);
+    oU2 = tk_align4(oU1 + (BF ? 1 : 2) * nfx * s1);
     oV = tk_align4(oU2 + n2 * s2);
     oC = tk_align4(oV + 8 * n3);
-    oW1 = tk_align4(oC + 8 * r2 * s1);
+    oW1 = tk_align4(oC + 8 * (r2 + (r2 & 1)) * s1);
     total = tk_align4(oW1 + nfx * fs);
   }
 };
@@ -141,6 +146,35 @@ __device__ __forceinline__ void tk_kloop(const float2* pa, const float2* pb0, co
   }
   for (; s < ks; ++s) {
     const typename X::A av = X::load_a(pa + s * X::KS, kg, ri);
+    D0 = X::mma(av, X::load_b(pb0 + s * X::KS, kg), D0);
+    if constexpr (TWO) D1 = X::mma(av, X::load_b(pb1 + s * X::KS, kg), D1);
+  }
+}
+
+// Same, both operands stacked (A rows hold plain (re, im) pairs): for the
+// product whose embedded operand was prepared in LDS.
+template <bool BF, int U, bool TWO>
+__device__ __forceinline__ void tk_kloop_st(const float2* pa, const float2* pb0, const float2* pb1, int ks, v4f& D0,
+                                            v4f& D1) {
+  typedef Cx<BF> X;
+  const int kg = (threadIdx.x & 63) >> 4;
+  int s = 0;
+  for (; s + U <= ks; s += U) {
+    typename X::B av[U], b0[U], b1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      av[u] = X::load_b(pa + (s + u) * X::KS, kg);
+      b0[u] = X::load_b(pb0 + (s + u) * X::KS, kg);
+      if constexpr (TWO) b1[u] = X::load_b(pb1 + (s + u) * X::KS, kg);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      D0 = X::mma(av[u], b0[u], D0);
+      if constexpr (TWO) D1 = X::mma(av[u], b1[u], D1);
+    }
+  }
+  for (; s < ks; ++s) {
+    const typename X::B av = X::load_b(pa + s * X::KS, kg);
     D0 = X::mma(av, X::load_b(pb0 + s * X::KS, kg), D0);
     if constexpr (TWO) D1 = X::mma(av, X::load_b(pb1 + s * X::KS, kg), D1);
   }
@@ -219,10 +253,21 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
   float2* sW1 = lds + L.oW1;
 
   // factors, and the zero padding of the C and W1 chunk rows (never rewritten)
+  // FP32: U1 enters the first product as its embedded operand (row (fx, 0)
+  // holds (re, -im), row (fx, 1) holds (im, re) of U1[fx][a]); bf16x3 keeps
+  // it stacked and embeds the C^T fragments instead (measured faster there)
   for (int e = tid; e < nfx * kp1; e += NT) {
     const int fx = e / kp1, k = e - fx * kp1;
-    stage<BF>(sU1, fx * s1 + k, k < r1 ? U1[(long long)(fx0 + fx) * r1 + k] : make_float2(0.f, 0.f));
+    const float2 u = k < r1 ? U1[(long long)(fx0 + fx) * r1 + k] : make_float2(0.f, 0.f);
+    if constexpr (BF) {
+      stage<BF>(sU1, fx * s1 + k, u);
+    } else {
+      stage<BF>(sU1, 2 * fx * s1 + k, make_float2(u.x, -u.y));
+      stage<BF>(sU1, (2 * fx + 1) * s1 + k, make_float2(u.y, u.x));
+    }
   }
+  if (r2 & 1)  // the padding b = r2 of the C chunk rows
+    for (int e = tid; e < 8 * kp1; e += NT) stage<BF>(sC, (8 * r2 + e / kp1) * s1 + e % kp1, make_float2(0.f, 0.f));
   for (int e = tid; e < n2 * kp2; e += NT) {
     const int fy = e / kp2, k = e - fy * kp2;
     stage<BF>(sU2, fy * s2 + k, k < r2 ? U2[fy * r2 + k] : make_float2(0.f, 0.f));
@@ -325,26 +370,66 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
       load_part(0, c0 + 8);
       load_v(c0 + 8);
     }
-    // first product, block-wide: W1^T[(b,cl)][fx] = sum_a C^T[(b,cl)][a] U1^T[a][fx];
-    // a task is one b (8 rows of C^T) against up to two 16-column fx tiles
-    {
-      const int fxc0 = min(j, nfx - 1), fxc1 = min(16 + j, nfx - 1);
-      const float2* pb0 = sU1 + fxc0 * s1;
-      const float2* pb1 = sU1 + fxc1 * s1;
-      for (int b = w; b < r2; b += NW) {
-        const float2* pa = sC + (8 * b + (i >> 1)) * s1;
-        v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
-        if (nfx > 16)
-          tk_kloop<BF, BF ? 1 : 4, true>(pa, pb0, pb1, ks1, D0, D1);
-        else
-          tk_kloop<BF, BF ? 1 : 4, false>(pa, pb0, pb1, ks1, D0, D1);
-        if (j < nfx) {
-          stage<BF>(sW1, j * fs + 2 * kg * s2 + b, make_float2(D0[0], D0[1]));
-          stage<BF>(sW1, j * fs + (2 * kg + 1) * s2 + b, make_float2(D0[2], D0[3]));
+    if constexpr (BF) {
+      // first product, block-wide: W1^T[(b,cl)][fx] = sum_a C^T[(b,cl)][a] U1^T[a][fx];
+      // a task is one b (8 rows of C^T) against up to two 16-column fx tiles
+      {
+        const int fxc0 = min(j, nfx - 1), fxc1 = min(16 + j, nfx - 1);
+        const float2* pb0 = sU1 + fxc0 * s1;
+        const float2* pb1 = sU1 + fxc1 * s1;
+        for (int b = w; b < r2; b += NW) {
+          const float2* pa = sC + (8 * b + (i >> 1)) * s1;
+          v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
+          if (nfx > 16)
+            tk_kloop<BF, BF ? 1 : 4, true>(pa, pb0, pb1, ks1, D0, D1);
+          else
+            tk_kloop<BF, BF ? 1 : 4, false>(pa, pb0, pb1, ks1, D0, D1);
+          if (j < nfx) {
+            stage<BF>(sW1, j * fs + 2 * kg * s2 + b, make_float2(D0[0], D0[1]));
+            stage<BF>(sW1, j * fs + (2 * kg + 1) * s2 + b, make_float2(D0[2], D0[3]));
+          }
+          if (16 + j < nfx) {
+            stage<BF>(sW1, (16 + j) * fs + 2 * kg * s2 + b, make_float2(D1[0], D1[1]));
+            stage<BF>(sW1, (16 + j) * fs + (2 * kg + 1) * s2 + b, make_float2(D1[2], D1[3]));
+          }
         }
-        if (16 + j < nfx) {
-          stage<BF>(sW1, (16 + j) * fs + 2 * kg * s2 + b, make_float2(D1[0], D1[1]));
-          stage<BF>(sW1, (16 + j) * fs + (2 * kg + 1) * s2 + b, make_float2(D1[2], D1[3]));
+      }
+    } else {
+      // first product, block-wide, with the small operand embedded:
+      //   [Re, Im] W1^T[(b,cl)][fx] = sum_(a,ki) [Re, Im] C^T[(b,cl)][(a,ki)] . E(U1^T)[(a,ki)][(fx,comp)]
+      // so the C^T fragments are loaded as they are.  A task is 16 rows of C^T
+      // (two b) against up to two 16-column tiles of (fx, comp).  Lane (g, j)
+      // ends with component j % 2 of four W1 entries; it swaps with lane j ^ 1 and
+      // writes two complex values.
+      {
+        const int nrt = (r2 + 1) >> 1, nct = (nfx + 7) >> 3, ncp = (nct + 1) >> 1;
+        const int comp = j & 1;
+        for (int task = w; task < nrt * ncp; task += NW) {
+          const int rt = task / ncp, ct0 = 2 * (task - rt * ncp), ct1 = min(ct0 + 1, nct - 1);
+          const float2* pa = sC + (16 * rt + i) * s1;
+          const int fxa = 8 * ct0 + (j >> 1), fxb = 8 * ct1 + (j >> 1);
+          const float2* pb0 = sU1 + (2 * min(fxa, nfx - 1) + comp) * s1;
+          const float2* pb1 = sU1 + (2 * min(fxb, nfx - 1) + comp) * s1;
+          v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
+          const bool two = ct0 + 1 < nct;
+          if (two)
+            tk_kloop_st<BF, 4, true>(pa, pb0, pb1, ks1, D0, D1);
+          else
+            tk_kloop_st<BF, 4, false>(pa, pb0, pb1, ks1, D0, D1);
+          auto put = [&](const v4f& D, int fx) {
+            float o[4];
+  #pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = __shfl_xor(D[r], 1);
+  #pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+              const float own = comp ? D[2 + rr] : D[rr], oth = comp ? o[2 + rr] : o[rr];
+              const int row = 4 * kg + 2 * comp + rr, b = 2 * rt + (row >> 3);
+              if (fx < nfx && b < r2)
+                stage<BF>(sW1, fx * fs + (row & 7) * s2 + b, comp ? make_float2(oth, own) : make_float2(own, oth));
+            }
+          };
+          put(D0, fxa);
+          if (two) put(D1, fxb);
         }
       }
     }
