@@ -114,16 +114,18 @@ __device__ __forceinline__ void block_cgemm(float2* lds, int M, int N, int K, in
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ unsigned bf16_bits_rne(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return u >> 16;
+typedef float v2f_t __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf_t __attribute__((ext_vector_type(2)));
+
+// Two floats to packed bf16 (round to nearest even): one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((v2f_t{a, b}), v2bf_t));
 }
 
 __device__ __forceinline__ uint2 split_bf3(float2 v) {
-  const unsigned rh = bf16_bits_rne(v.x), ih = bf16_bits_rne(v.y);
-  const float rl = v.x - __uint_as_float(rh << 16), il = v.y - __uint_as_float(ih << 16);
-  return make_uint2(rh | (ih << 16), bf16_bits_rne(rl) | (bf16_bits_rne(il) << 16));
+  const unsigned h = cvt_pk_bf16(v.x, v.y);
+  const float rl = v.x - __uint_as_float(h << 16), il = v.y - __uint_as_float(h & 0xFFFF0000u);
+  return make_uint2(h, cvt_pk_bf16(rl, il));
 }
 
 // Store of a staged operand value: complex64 as is, or split into bf16 hi/lo.
