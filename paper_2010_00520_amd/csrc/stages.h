@@ -148,7 +148,8 @@ struct ChunkPrefetch {
   }
 };
 
-template <int FMT, int T, int CB, int NW, bool BF>
+// N2C: n2 when known at compile time (fused kernels), else 0.
+template <int FMT, int T, int CB, int NW, bool BF, int N2C = 0>
 __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, int p, int q0, float2* lds) {
   constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
@@ -174,7 +175,7 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
     const int KC = a.KC, kcs = 31 - __builtin_clz(KC);  // KC is a power of two
     if constexpr (FMT == ZF_TUCKER) {
       if (a.tk2) {
-        restore_tucker<T, CB, NW, BF>(acc, a, d, q0, lds);
+        restore_tucker<T, CB, NW, BF, N2C>(acc, a, d, q0, lds);
         return;
       }
       const int r1 = d[4], r2 = d[5], r3 = d[6];
@@ -520,7 +521,7 @@ __device__ __forceinline__ void fused_item(const ZArgs& a, const RhsPtrs& P, flo
   const int w = threadIdx.x >> 6;
   const int p = a.perm ? a.perm[it] : it;
   v4f acc[T][CB];
-  restore_tile<FMT, T, CB, NW, BF>(acc, a, p, 0, lds);
+  restore_tile<FMT, T, CB, NW, BF, N>(acc, a, p, 0, lds);
   const long long blk = (long long)K * K * K;
   if constexpr (N == 32 && CB % 4 == 0) {
     float2 tz[CB / 4][32];

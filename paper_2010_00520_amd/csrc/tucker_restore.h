@@ -229,13 +229,18 @@ struct TkCoreSrc {
   }
 };
 
-template <int T, int CB, int NW, bool BF>
+// N2C: the grid's n2 when the caller knows it at compile time (fused
+// kernels), else 0.  With n2 a multiple of 32 every pair of 16-pencil blocks
+// lies in one x-row, and the per-pair row test and its fallback drop out of
+// the code (keeping the kernel's chunk loop within the instruction cache).
+template <int T, int CB, int NW, bool BF, int N2C = 0>
 __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a, const int* d, int q0,
                                                float2* lds) {
   typedef Cx<BF> X;
   constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T, PF = 4;
+  constexpr bool kPairs = N2C > 0 && N2C % 32 == 0 && CB % 2 == 0;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, kg = l >> 4, i = l & 15, j = l & 15;
-  const int n2 = a.n2;
+  const int n2 = N2C > 0 ? N2C : a.n2;
   const int r1 = d[4], r2 = d[5], r3 = d[6];
   const float2* C = a.cbase + d[0];
   const float2* U1 = a.fbase + d[1];
@@ -318,9 +323,11 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
     }
   };
   auto load_v = [&](int c0) {
+    int to = tid;
+    asm volatile("" : "+v"(to));
 #pragma unroll
     for (int u = 0; u < VP; ++u) {
-      const int e = tid + u * NT, fz = e >> 3, cl = e & 7;
+      const int e = to + u * NT, fz = e >> 3, cl = e & 7;
       const float2 v = (e < 8 * N3 && c0 + cl < r3) ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f);
       vx[u] = v.x;
       vy[u] = v.y;
@@ -366,9 +373,9 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
         for (int s4 = 0; s4 < 4; ++s4) a3f[t][s4] = embed_a(sV[fz * 8 + 2 * kg + (s4 >> 1)], ri, s4 & 1);
       }
     }
-    if (more) {
-      load_part(0, c0 + 8);
+    if (more) {  // U3 columns first: nothing of theirs may wait behind the core loads
       load_v(c0 + 8);
+      load_part(0, c0 + 8);
     }
     if constexpr (BF) {
       // first product, block-wide: W1^T[(b,cl)][fx] = sum_a C^T[(b,cl)][a] U1^T[a][fx];
@@ -411,7 +418,7 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
           const float2* pb0 = sU1 + (2 * min(fxa, nfx - 1) + comp) * s1;
           const float2* pb1 = sU1 + (2 * min(fxb, nfx - 1) + comp) * s1;
           v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
-          const bool two = ct0 + 1 < nct;
+          const bool two = (nct % 2 == 0) || ct0 + 1 < nct;  // even nct: ct0 <= nct - 2
           if (two)
             tk_kloop_st<BF, 4, true>(pa, pb0, pb1, ks1, D0, D1);
           else
@@ -460,6 +467,19 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
     };
 #pragma unroll
     for (int c = 0; c < CB; c += 2) {
+      if constexpr (kPairs) {
+        // blocks c, c+1 are 32 consecutive pencils starting on a multiple of 32
+        const int qb = q0 + (w * CB + c) * 16, fx = qb / n2 - fx0, fy = qb - (qb / n2) * n2 + j;
+        v4f D0, D1;
+        tk_wgemm2<BF>(sW1, sU2, s2, L.fs, ks2, fx, fy, fy + 16, D0, D1);
+        finish(c, D0);
+        finish(c + 1, D1);
+        if (more && part < nparts) {
+          store_part(part);
+          if (++part < nparts) load_part(part, c0 + 8);
+        }
+        continue;
+      }
       // pencils of blocks c and c+1: x-row of lane 0 (fa), of lane 15 (fb); a
       // block spans at most two x-rows since n2 >= 8
       int fa[2], fb[2], fxj[2], fyj[2];
