@@ -144,8 +144,11 @@ __device__ __forceinline__ v4f mfma_bf16(v4u a, v4u b, v4f c) {
 
 // Real embedding of a packed (re, im) bf16 dword for the A operand:
 // row ri = 0 takes (re, -im), row ri = 1 takes (im, re).
+// Branch-free (a select here is compiled into divergent branches that wait
+// for each LDS load separately): rotate by 16 ri, then flip the sign bit
+// when ri == 0.
 __device__ __forceinline__ unsigned embed_a_bf(unsigned d, int ri) {
-  return ri == 0 ? (d ^ 0x80000000u) : ((d >> 16) | (d << 16));
+  return __builtin_amdgcn_alignbit(d, d, (unsigned)ri << 4) ^ ((unsigned)(ri ^ 1) << 31);
 }
 
 // acc += A' B' for one 16x16x32 bf16 K-step in split arithmetic.
