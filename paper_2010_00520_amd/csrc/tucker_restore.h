@@ -62,20 +62,20 @@ struct Cx<true> {
   static constexpr int KS = 16;
   typedef BfFrag A;
   typedef BfFrag B;
+  // p + 4 kg starts a quartet (see stq): hi parts of its 4 k, then lo parts
   static __device__ __forceinline__ A load_a(const float2* p, int kg, int ri) {
     const uint4* q = reinterpret_cast<const uint4*>(p + 4 * kg);
     const uint4 x = q[0], y = q[1];
     A r;
-    r.hi = v4u{embed_a_bf(x.x, ri), embed_a_bf(x.z, ri), embed_a_bf(y.x, ri), embed_a_bf(y.z, ri)};
-    r.lo = v4u{embed_a_bf(x.y, ri), embed_a_bf(x.w, ri), embed_a_bf(y.y, ri), embed_a_bf(y.w, ri)};
+    r.hi = v4u{embed_a_bf(x.x, ri), embed_a_bf(x.y, ri), embed_a_bf(x.z, ri), embed_a_bf(x.w, ri)};
+    r.lo = v4u{embed_a_bf(y.x, ri), embed_a_bf(y.y, ri), embed_a_bf(y.z, ri), embed_a_bf(y.w, ri)};
     return r;
   }
   static __device__ __forceinline__ B load_b(const float2* p, int kg) {
-    const uint4* q = reinterpret_cast<const uint4*>(p + 4 * kg);
-    const uint4 x = q[0], y = q[1];
+    const v4u* q = reinterpret_cast<const v4u*>(p + 4 * kg);
     B r;
-    r.hi = v4u{x.x, x.z, y.x, y.z};
-    r.lo = v4u{x.y, x.w, y.y, y.w};
+    r.hi = q[0];
+    r.lo = q[1];
     return r;
   }
   static __device__ __forceinline__ B zero_b() {
@@ -100,6 +100,23 @@ __host__ __device__ __forceinline__ int tk_stride(int r) {
   return BF ? tk_kpad<BF>(r) + 2 : tk_kpad<BF>(r) + 1;
 }
 __host__ __device__ __forceinline__ int tk_align4(int e) { return (e + 3) & ~3; }
+
+// Store of operand value v at position k of an LDS row (row start 16-byte
+// aligned).  FP32: complex64 at row[k].  BF16X3: the row is cut into
+// quartets of 4 k (32 bytes); a quartet holds the four split hi dwords, then
+// the four lo dwords, so one K-step fragment is two 16-byte loads that land
+// in the MFMA operand registers as they are.
+template <bool BF>
+__device__ __forceinline__ void stq(float2* row, int k, float2 v) {
+  if constexpr (BF) {
+    const uint2 h = split_bf3(v);
+    unsigned* u = reinterpret_cast<unsigned*>(row) + 8 * (k >> 2) + (k & 3);
+    u[0] = h.x;
+    u[4] = h.y;
+  } else {
+    row[k] = v;
+  }
+}
 
 // LDS layout (complex elements) of the Tucker restoration of a tile with nfx
 // x-rows: U1 (FP32: embedded, two rows per x-row), U2, U3 columns of the
@@ -223,9 +240,11 @@ struct TkCoreSrc {
     const int cl = e & 7, ab = e >> 3;
     return cl < kc ? C[c0 + ab * r3 + cl] : make_float2(0.f, 0.f);
   }
-  __device__ __forceinline__ int lds_index(int e, int s1) const {
-    const int cl = e & 7, ab = e >> 3, a = (int)__umulhi((unsigned)ab, m), b = ab - a * r2;
-    return (8 * b + cl) * s1 + a;
+  // LDS row (8b + cl) and column a of element e
+  __device__ __forceinline__ int lds_row(int e, int& a) const {
+    const int cl = e & 7, ab = e >> 3;
+    a = (int)__umulhi((unsigned)ab, m);
+    return 8 * (ab - a * r2) + cl;
   }
 };
 
@@ -265,27 +284,27 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
     const int fx = e / kp1, k = e - fx * kp1;
     const float2 u = k < r1 ? U1[(long long)(fx0 + fx) * r1 + k] : make_float2(0.f, 0.f);
     if constexpr (BF) {
-      stage<BF>(sU1, fx * s1 + k, u);
+      stq<BF>(sU1 + fx * s1, k, u);
     } else {
-      stage<BF>(sU1, 2 * fx * s1 + k, make_float2(u.x, -u.y));
-      stage<BF>(sU1, (2 * fx + 1) * s1 + k, make_float2(u.y, u.x));
+      stq<BF>(sU1 + 2 * fx * s1, k, make_float2(u.x, -u.y));
+      stq<BF>(sU1 + (2 * fx + 1) * s1, k, make_float2(u.y, u.x));
     }
   }
   if (r2 & 1)  // the padding b = r2 of the C chunk rows
-    for (int e = tid; e < 8 * kp1; e += NT) stage<BF>(sC, (8 * r2 + e / kp1) * s1 + e % kp1, make_float2(0.f, 0.f));
+    for (int e = tid; e < 8 * kp1; e += NT) stq<BF>(sC + (8 * r2 + e / kp1) * s1, e % kp1, make_float2(0.f, 0.f));
   for (int e = tid; e < n2 * kp2; e += NT) {
     const int fy = e / kp2, k = e - fy * kp2;
-    stage<BF>(sU2, fy * s2 + k, k < r2 ? U2[fy * r2 + k] : make_float2(0.f, 0.f));
+    stq<BF>(sU2 + fy * s2, k, k < r2 ? U2[fy * r2 + k] : make_float2(0.f, 0.f));
   }
   if (kp1 > r1)
     for (int e = tid; e < 8 * r2 * (kp1 - r1); e += NT) {
       const int row = e / (kp1 - r1);
-      stage<BF>(sC, row * s1 + r1 + (e - row * (kp1 - r1)), make_float2(0.f, 0.f));
+      stq<BF>(sC + row * s1, r1 + (e - row * (kp1 - r1)), make_float2(0.f, 0.f));
     }
   if (kp2 > r2)
     for (int e = tid; e < 8 * nfx * (kp2 - r2); e += NT) {
       const int row = e / (kp2 - r2);
-      stage<BF>(sW1, (row >> 3) * fs + (row & 7) * s2 + r2 + (e - row * (kp2 - r2)), make_float2(0.f, 0.f));
+      stq<BF>(sW1 + (row >> 3) * fs + (row & 7) * s2, r2 + (e - row * (kp2 - r2)), make_float2(0.f, 0.f));
     }
 
   // Core chunks are staged through registers in parts of PF elements per
@@ -319,7 +338,11 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int e = P * PART + to + u * NT;
-      if (e < csz) stage<BF>(sC, src.lds_index(e, s1), make_float2(px[u], py[u]));
+      if (e < csz) {
+        int ka;
+        const int row = src.lds_row(e, ka);
+        stq<BF>(sC + row * s1, ka, make_float2(px[u], py[u]));
+      }
     }
   };
   auto load_v = [&](int c0) {
@@ -337,7 +360,7 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
 #pragma unroll
     for (int u = 0; u < VP; ++u) {
       const int e = tid + u * NT;
-      if (e < 8 * N3) stage<BF>(sV, e, make_float2(vx[u], vy[u]));
+      if (e < 8 * N3) stq<BF>(sV + (e & ~7), e & 7, make_float2(vx[u], vy[u]));
     }
   };
   load_v(0);
@@ -365,9 +388,11 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
     for (int t = 0; t < T; ++t) {
       const int fz = 8 * t + (i >> 1), ri = i & 1;
       if constexpr (BF) {
-        const uint2* pv = reinterpret_cast<const uint2*>(sV) + fz * 8 + 2 * kg;
-        const uint2 v0 = pv[0], v1 = pv[1];
-        a3b[t] = v4u{embed_a_bf(v0.x, ri), embed_a_bf(v1.x, ri), embed_a_bf(v0.y, ri), embed_a_bf(v1.y, ri)};
+        // c = 2kg, 2kg+1 of row fz: quartet kg/2, positions 2(kg%2), +1
+        const uint2* pv = reinterpret_cast<const uint2*>(reinterpret_cast<const unsigned*>(sV + fz * 8) +
+                                                         8 * (kg >> 1) + 2 * (kg & 1));
+        const uint2 vh = pv[0], vl = pv[2];
+        a3b[t] = v4u{embed_a_bf(vh.x, ri), embed_a_bf(vh.y, ri), embed_a_bf(vl.x, ri), embed_a_bf(vl.y, ri)};
       } else {
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) a3f[t][s4] = embed_a(sV[fz * 8 + 2 * kg + (s4 >> 1)], ri, s4 & 1);
@@ -392,12 +417,12 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
           else
             tk_kloop<BF, BF ? 1 : 4, false>(pa, pb0, pb1, ks1, D0, D1);
           if (j < nfx) {
-            stage<BF>(sW1, j * fs + 2 * kg * s2 + b, make_float2(D0[0], D0[1]));
-            stage<BF>(sW1, j * fs + (2 * kg + 1) * s2 + b, make_float2(D0[2], D0[3]));
+            stq<BF>(sW1 + j * fs + 2 * kg * s2, b, make_float2(D0[0], D0[1]));
+            stq<BF>(sW1 + j * fs + (2 * kg + 1) * s2, b, make_float2(D0[2], D0[3]));
           }
           if (16 + j < nfx) {
-            stage<BF>(sW1, (16 + j) * fs + 2 * kg * s2 + b, make_float2(D1[0], D1[1]));
-            stage<BF>(sW1, (16 + j) * fs + (2 * kg + 1) * s2 + b, make_float2(D1[2], D1[3]));
+            stq<BF>(sW1 + (16 + j) * fs + 2 * kg * s2, b, make_float2(D1[0], D1[1]));
+            stq<BF>(sW1 + (16 + j) * fs + (2 * kg + 1) * s2, b, make_float2(D1[2], D1[3]));
           }
         }
       }
@@ -432,7 +457,7 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
               const float own = comp ? D[2 + rr] : D[rr], oth = comp ? o[2 + rr] : o[rr];
               const int row = 4 * kg + 2 * comp + rr, b = 2 * rt + (row >> 3);
               if (fx < nfx && b < r2)
-                stage<BF>(sW1, fx * fs + (row & 7) * s2 + b, comp ? make_float2(oth, own) : make_float2(own, oth));
+                stq<BF>(sW1 + fx * fs + (row & 7) * s2, b, comp ? make_float2(oth, own) : make_float2(own, oth));
             }
           };
           put(D0, fxa);
