@@ -134,6 +134,7 @@ struct tfmm_ctx_s {
   int device = 0;
   bool no_fused = false;               // TFMM_NO_FUSED=1: always use the three-pass pipeline
   bool no_tk2 = false;                 // TFMM_NO_TK2=1: Tucker restoration through LDS-staged products
+  size_t hcap = (size_t)256 << 20;     // TFMM_HCAP_MB: three-pass half-spectrum chunk
   size_t budget = 0, used = 0;
   std::recursive_mutex mu;
   // translation scratch, one per stream slot (slot 0 = tfmm_translate; 1..S = scheduler streams)
@@ -627,7 +628,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], K3 = op->K[2], nd = op->ndir;
   const size_t per_dir_rhs = (size_t)K3 * op->nq * sizeof(float2);
   const int nr_total = (int)As.size();
-  const size_t hcap = (size_t)256 << 20;  // half-spectrum scratch per chunk
+  const size_t hcap = c->hcap;  // half-spectrum scratch per chunk
   const int rhs_group = std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH);
   int ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, hcap / (per_dir_rhs * rhs_group)));
   const size_t hbytes = op->fused ? 0 : per_dir_rhs * rhs_group * ndl;
@@ -937,6 +938,10 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   c->no_fused = nf && nf[0] == '1';
   const char* nt = std::getenv("TFMM_NO_TK2");
   c->no_tk2 = nt && nt[0] == '1';
+  if (const char* hc = std::getenv("TFMM_HCAP_MB")) {
+    const long v = std::strtol(hc, nullptr, 10);
+    if (v >= 1 && v <= 65536) c->hcap = (size_t)v << 20;
+  }
   const char* tp = std::getenv("TFMM_TUNE_CACHE");
   if (tp && tp[0]) {
     c->tune_path = tp;

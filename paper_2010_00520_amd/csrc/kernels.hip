@@ -289,52 +289,133 @@ size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf) {
 }
 
 // ---------------------------------------------------------------------------
-// a1: batched complex GEMM on global memory (one 8 x 16 complex tile per wave).
+// a1: batched complex GEMM C[b] = A[b] B[b] (complex64, arbitrary element
+// strides), LDS-tiled on 16x16x4 f32 MFMAs.  A block of four waves owns a
+// BM x BN complex tile of C (waves arranged WGM x WGN, each TM x TN MFMA tiles
+// of 8 x 16 complex); K is staged in chunks of KC complex through LDS, the
+// next chunk prefetched into registers while the current one is multiplied.
+// Real embedding as elsewhere: A rows (m, re/im) x k columns (k, re/im) of
+// [[re, -im], [im, re]], B stacked (k, re/im); a lane's A fragment is one
+// float picked by address (component ri ^ ki) with the sign applied by xor.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(TFMM_BLOCK) void k_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C,
-                                                      long long cs0, long long cs1, long long csb) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int tmN = (M + 7) >> 3, tnN = (N + 15) >> 4;
-  const long long per = (long long)tmN * tnN;
-  const long long tile = (long long)blockIdx.x * TFMM_NWAVES + w;
-  if (tile >= per * nb) return;  // wave-uniform
-  const int bat = (int)(tile / per);
-  const int rem = (int)(tile - (long long)bat * per);
-  const int tm = rem / tnN, tn = rem - tm * tnN;
-  const int kofs = (l >> 4) >> 1, ki = (l >> 4) & 1, ari = l & 1;
-  const int am = tm * 8 + ((l & 15) >> 1), bn = tn * 16 + (l & 15);
-  const bool aok = am < M, bok = bn < N;
-  const float2* ap = A.p + (long long)am * A.s0 + (long long)bat * A.sb;
-  const float2* bp = B.p + (long long)bn * B.s1 + (long long)bat * B.sb;
-  v4f acc = {0.f, 0.f, 0.f, 0.f};
-  const int ks = (K + 1) >> 1;
-  for (int s = 0; s < ks; ++s) {
-    const int k = 2 * s + kofs;
-    float av = 0.f, bv = 0.f;
-    if (aok && k < K) {
-      const float2 v = ap[(long long)k * A.s1];
-      av = ari == 0 ? (ki == 0 ? v.x : -v.y) : (ki == 0 ? v.y : v.x);
+template <int TM, int TN, int WGM, int WGN>
+__global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, GOp A, GOp B, float2* __restrict__ C,
+                                               long long cs0, long long cs1, long long csb, int tiles_n) {
+  static_assert(WGM * WGN == 4, "four waves per block");
+  constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN, KC = 16;
+  constexpr int AS = KC + 1;                          // A row stride (complex)
+  constexpr int BS = BN + ((BN % 32) == 0 ? 16 : 0);  // B row stride: k rows of a fragment in other banks
+  constexpr int EA = BM * KC / 256, EB = KC * BN / 256;
+  static_assert(EA * 256 == BM * KC && EB * 256 == KC * BN, "whole tiles per thread");
+  __shared__ float2 sA[BM * AS];
+  __shared__ float2 sB[KC * BS];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tmb = blockIdx.x / tiles_n, tnb = blockIdx.x - tmb * tiles_n;
+  const int m0 = tmb * BM, n0 = tnb * BN;
+  const float2* __restrict__ Ap = A.p + (long long)blockIdx.y * A.sb;
+  const float2* __restrict__ Bp = B.p + (long long)blockIdx.y * B.sb;
+  // global -> register staging: the contiguous index of each operand varies
+  // fastest across threads
+  const bool akf = A.s1 == 1, bkf = B.s0 == 1;
+  float2 ra[EA], rb[EB];
+  auto a_pos = [&](int e, int& mm, int& kk) {
+    if (akf) { kk = e % KC; mm = e / KC; } else { mm = e % BM; kk = e / BM; }
+  };
+  auto b_pos = [&](int e, int& kk, int& nn) {
+    if (bkf) { kk = e % KC; nn = e / KC; } else { nn = e % BN; kk = e / BN; }
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      int mm, kk;
+      a_pos(tid + 256 * u, mm, kk);
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[u] = (gm < M && gk < K) ? Ap[(long long)gm * A.s0 + (long long)gk * A.s1] : make_float2(0.f, 0.f);
     }
-    if (bok && k < K) {
-      const float2 v = bp[(long long)k * B.s0];
-      bv = ki == 0 ? v.x : v.y;
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      int kk, nn;
+      b_pos(tid + 256 * u, kk, nn);
+      const int gk = k0 + kk, gn = n0 + nn;
+      rb[u] = (gk < K && gn < N) ? Bp[(long long)gk * B.s0 + (long long)gn * B.s1] : make_float2(0.f, 0.f);
     }
-    acc = mfma4(av, bv, acc);
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      int mm, kk;
+      a_pos(tid + 256 * u, mm, kk);
+      sA[mm * AS + kk] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      int kk, nn;
+      b_pos(tid + 256 * u, kk, nn);
+      sB[kk * BS + nn] = rb[u];
+    }
+  };
+  const int wm = w / WGN, wn = w - wm * WGN;
+  const int i = l & 15, g = l >> 4, kofs = g >> 1, ki = g & 1, ri = i & 1;
+  const int comp = ri ^ ki;
+  const unsigned neg = (ri == 0 && ki == 1) ? 0x80000000u : 0u;
+  const float* fa = reinterpret_cast<const float*>(sA) + 2 * ((wm * TM * 8 + (i >> 1)) * AS + kofs) + comp;
+  const float* fb = reinterpret_cast<const float*>(sB) + 2 * (kofs * BS + wn * TN * 16 + i) + ki;
+  v4f acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int nk = (K + KC - 1) / KC;
+  load(0);
+  for (int c = 0; c < nk; ++c) {
+    __syncthreads();  // the previous chunk's fragments have been read
+    store();
+    __syncthreads();
+    if (c + 1 < nk) load((c + 1) * KC);
+#pragma unroll
+    for (int s = 0; s < KC / 2; ++s) {
+      float af[TM], bf[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) af[a] = __uint_as_float(__float_as_uint(fa[2 * (a * 8 * AS + 2 * s)]) ^ neg);
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bf[b] = fb[2 * (2 * s * BS + b * 16)];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = mfma4(af[a], bf[b], acc[a][b]);
+    }
   }
-  const int cn = tn * 16 + (l & 15), cm0 = tm * 8 + 2 * (l >> 4);
-  if (cn < N) {
-    float2* cp = C + (long long)cn * cs1 + (long long)bat * csb;
-    if (cm0 < M) cp[(long long)cm0 * cs0] = make_float2(acc[0], acc[1]);
-    if (cm0 + 1 < M) cp[(long long)(cm0 + 1) * cs0] = make_float2(acc[2], acc[3]);
-  }
+  float2* Cb = C + (long long)blockIdx.y * csb;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int cn = n0 + (wn * TN + b) * 16 + i, cm0 = m0 + (wm * TM + a) * 8 + 2 * g;
+      if (cn < N) {
+        float2* cp = Cb + (long long)cn * cs1;
+        if (cm0 < M) cp[(long long)cm0 * cs0] = make_float2(acc[a][b][0], acc[a][b][1]);
+        if (cm0 + 1 < M) cp[(long long)(cm0 + 1) * cs0] = make_float2(acc[a][b][2], acc[a][b][3]);
+      }
+    }
+}
+
+template <int TM, int TN, int WGM, int WGN>
+static hipError_t run_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
+                            long long csb, hipStream_t st) {
+  constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN;
+  const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN>), dim3((unsigned)(tiles_m * tiles_n), (unsigned)nb), dim3(256), 0,
+                     st, M, N, K, A, B, C, cs0, cs1, csb, tiles_n);
+  return hipGetLastError();
 }
 
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                         long long csb, hipStream_t st) {
-  const long long tiles = (long long)((M + 7) / 8) * ((N + 15) / 16) * nb;
-  const long long blocks = (tiles + TFMM_NWAVES - 1) / TFMM_NWAVES;
-  hipLaunchKernelGGL(k_cgemm, dim3((unsigned)blocks), dim3(TFMM_BLOCK), 0, st, M, N, K, nb, A, B, C, cs0, cs1, csb);
-  return hipGetLastError();
+  if (M <= 0 || N <= 0 || nb <= 0) return hipSuccess;
+  if (nb > 65535) return hipErrorInvalidValue;
+  if (N <= 16) return run_cgemm<4, 1, 4, 1>(M, N, K, nb, A, B, C, cs0, cs1, csb, st);   // 128 x 16
+  if (M <= 16) return run_cgemm<2, 2, 1, 4>(M, N, K, nb, A, B, C, cs0, cs1, csb, st);   // 16 x 128
+  return run_cgemm<4, 2, 2, 2>(M, N, K, nb, A, B, C, cs0, cs1, csb, st);                // 64 x 64
 }
 
 }  // namespace tfmm
