@@ -49,7 +49,8 @@ def parse():
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
                     help="override the restoration arithmetic")
     ap.add_argument("--autotune", action="store_true",
-                    help="run tfmm_autotune for the workload's RHS count before timing")
+                    help="run tfmm_autotune for the workload's RHS count before timing "
+                         "(always on for the batching and precision workloads)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     return ap.parse_args()
@@ -301,6 +302,7 @@ def bench_precision(args):
     rows = []
     with P.Context(0) as ctx:
         full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
+        ctx.autotune(full, nrhs=nrhs, reps=10)  # tiles autotuned on both sides of the comparison
         Bf = torch.zeros_like(A)
         ms_f, _, _ = time_steps(ctx, full, A, Bf, args.steps, args.warmup, torch)
         bytes_full = full.info()["bytes_stored"]
@@ -315,6 +317,7 @@ def bench_precision(args):
                 ranks, data = list(info["ranks"][:nr]), op.export()
                 for prec in ("fp32", "bf16x3"):
                     o = op if prec == "fp32" else ctx.import_factors(w.K, w.L, fmt, ranks, data, prec=prec)
+                    plan, _ = ctx.autotune(o, nrhs=nrhs, reps=10)
                     B = torch.zeros_like(A)
                     ms, lat, kt = time_steps(ctx, o, A, B, args.steps, args.warmup, torch)
                     Bn = B.cpu().numpy().astype(np.complex128)
@@ -324,7 +327,8 @@ def bench_precision(args):
                                  "memory_fraction": info["bytes_stored"] / bytes_full, "ranks": ranks,
                                  "rel_err_fro_setup": info["rel_err_fro"], "setup_s": setup_s,
                                  "rel_err_per_rhs_max_over_sample": per_rhs,
-                                 "within_10gamma": bool(max(per_rhs) <= 10 * tol + 1e-6), "kernels": kt})
+                                 "within_10gamma": bool(max(per_rhs) <= 10 * tol + 1e-6), "kernels": kt,
+                                 "plan": plan})
                     if o is not op:
                         o.release()
                 op.release()
@@ -378,12 +382,15 @@ def main():
             t0 = time.perf_counter()
             op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
             setup_s = time.perf_counter() - t0
-            tuned = ctx.autotune(op, nrhs=w.nrhs, reps=10) if args.autotune else None
+            tune = args.autotune or args.workload == "batching"
+            tuned = ctx.autotune(op, nrhs=w.nrhs, reps=10) if tune else None
             ms, lat, kt = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
             res[prec] = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": op.ranks(), "setup_s": setup_s,
                          "plan": op.plan(), "autotune": tuned, "B": B.cpu().numpy().astype(np.complex128)}
             op.release()
         full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
+        if args.autotune or args.workload == "batching":
+            ctx.autotune(full, nrhs=w.nrhs, reps=10)
         Bf = torch.zeros_like(A)
         ms_f, lat_f, kt_f = time_steps(ctx, full, A, Bf, args.steps, args.warmup, torch)
         finfo = full.info()

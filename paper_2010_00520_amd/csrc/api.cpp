@@ -337,6 +337,8 @@ tfmm_status plan_zstage(tfmm_op op) {
     op->KC = KC;
     op->lds = (int)need;
   }
+  // the z-stage's pencil transform reuses the restoration's LDS
+  op->lds = (int)std::max<size_t>((size_t)op->lds, tfmm::zpencil_lds_bytes(n3, op->cb));
   // fused path: cubic grids whose half spectrum (n*n*zp complex64) fits in LDS
   op->fused = false;
   if (!op->ctx->no_fused && ch.fused != 0 && n1 == n2 && n2 == n3 &&

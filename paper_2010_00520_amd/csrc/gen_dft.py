@@ -8,7 +8,7 @@ Writes dft_codelets.h: for each line length n used by the padded FFT grids,
   dft_inv_<n>(x, y)   unnormalised inverse DFT (exp(+2 pi i jk/n)) of n values,
                       of which only the first n/2 outputs are produced (the crop
                       back to the box grid);
-  dft_full_fwd_<t> / dft_full_inv_<t>   plain length-t DFTs (t <= 8).
+  dft_full_fwd_<t> / dft_full_inv_<t>   plain length-t DFTs (t <= 8, 12, 16, 24, 32).
 
 Each codelet is a recursive decimation-in-time mixed-radix (4, 2, 3) DFT
 unrolled into SSA statements on float2 registers.  Known-zero inputs are
@@ -25,7 +25,7 @@ import sys
 import numpy as np
 
 LINE_SIZES = (2, 4, 6, 8, 12, 16, 24, 32, 48, 64)
-SMALL_SIZES = (1, 2, 3, 4, 5, 6, 7, 8, 16)
+SMALL_SIZES = (1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32)
 
 
 def f32hex(v: float) -> str:
@@ -198,9 +198,14 @@ def main(out_path):
                      f"  __device__ __forceinline__ static void fwd(const float2* x, float2* y) {{ dft_fwd_{n}(x, y); }}\n"
                      f"  __device__ __forceinline__ static void inv(const float2* x, float2* y) {{ dft_inv_{n}(x, y); }}\n"
                      f"}};\n")
+    parts.append("template <int N> struct DftFull;\n")
     for t in SMALL_SIZES:
         parts.append(codelet(f"dft_full_fwd_{t}", t, t, t, -1, f"full forward DFT of length {t}"))
         parts.append(codelet(f"dft_full_inv_{t}", t, t, t, +1, f"full inverse DFT of length {t} (unnormalised)"))
+        parts.append(f"template <> struct DftFull<{t}> {{\n"
+                     f"  __device__ __forceinline__ static void fwd(const float2* x, float2* y) {{ dft_full_fwd_{t}(x, y); }}\n"
+                     f"  __device__ __forceinline__ static void inv(const float2* x, float2* y) {{ dft_full_inv_{t}(x, y); }}\n"
+                     f"}};\n")
     src = "\n".join(parts)
     with open(out_path, "w") as f:
         f.write(src)

@@ -44,6 +44,9 @@ struct ZArgs {
 // LDS bytes a restoration of a qt-pencil tile needs for a format / ranks /
 // chunk (host-side planning; qt = n1*n2 for the fused kernel).
 size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1, int r2);
+// LDS of the three-pass z-stage's pencil transform: four waves, 16 cb pencils
+// each, rows of n3 + 1 complex.
+inline size_t zpencil_lds_bytes(int n3, int cb) { return (size_t)4 * 16 * cb * (n3 + 1) * 8; }
 // LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf);
 

@@ -443,6 +443,61 @@ __device__ __forceinline__ void zfft_pencils32(const float2 (&tz)[NP][32], float
 }
 
 // ---------------------------------------------------------------------------
+// z-stage of the three-pass pipeline with whole pencils per lane.  The
+// restored tile (wave w: 16 CB pencils, lane (g, j) of column block c holding
+// fz = 8t + 2g + {0,1} of pencil 16c + j) is written once to an LDS region of
+// the wave, one row of N3 frequencies per pencil (odd row stride); lane l then
+// owns pencil l of the wave.  Per RHS a lane reads its K3 = N3/2 nonzero
+// inputs (coalesced over lanes: consecutive pencils are consecutive in H),
+// splits the pruned N3-point transform into even and odd outputs,
+//   X[2m] = DFT_K3(x)[m],  X[2m+1] = DFT_K3(x[z] w^z)[m],
+//   y[z'] = IDFT_K3(P_even)[z'] + w^-z' IDFT_K3(P_odd)[z'],   z' < K3,
+// (w = exp(-2 pi i / N3), P = X * T~), and writes its K3 outputs back.
+// ---------------------------------------------------------------------------
+template <int T, int CB>
+__device__ __forceinline__ void zstage_pencils(const v4f (&acc)[T][CB], const ZArgs& a, int pl, int q0,
+                                               float2* lds) {
+  constexpr int N3 = 8 * T, K = 4 * T, PS = N3 + 1, NPW = 16 * CB;
+  static_assert(NPW <= 64, "one pencil per lane");  // LDS: zpencil_lds_bytes
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, j = l & 15;
+  float2* reg = lds + w * (NPW * PS);
+  __syncthreads();  // the restoration is done with its LDS
+#pragma unroll
+  for (int c = 0; c < CB; ++c)
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        reg[(c * 16 + j) * PS + 8 * t + 2 * g + e] = make_float2(acc[t][c][2 * e], acc[t][c][2 * e + 1]);
+  __syncthreads();
+  const int q = q0 + w * NPW + l;
+  if (l < NPW && q < a.nq) {
+    const float2* tz = reg + l * PS;
+    const float2* wz = a.roots;  // wz[z] = w^z
+    const long long zs = a.nq;
+    for (int s = 0; s < a.nrhs; ++s) {
+      float2* h = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq) + q;
+      float2 x[K], E[K], ye[K];
+#pragma unroll
+      for (int z = 0; z < K; ++z) x[z] = h[z * zs];
+      DftFull<K>::fwd(x, E);
+#pragma unroll
+      for (int z = 0; z < K; ++z) x[z] = cmul(x[z], wz[z]);
+#pragma unroll
+      for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m]);
+      DftFull<K>::inv(E, ye);
+      DftFull<K>::fwd(x, E);
+#pragma unroll
+      for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m + 1]);
+      DftFull<K>::inv(E, x);
+#pragma unroll
+      for (int z = 0; z < K; ++z) h[z * zs] = cadd(ye[z], cmulconj(x[z], wz[z]));
+    }
+  }
+  __syncthreads();  // the region is reused by the next item's restoration
+}
+
+// ---------------------------------------------------------------------------
 // Work items of the z-stage and fused kernels.  Block b starts with item b;
 // when the launch has more items than resident blocks (a.counter set), each
 // block then takes further items from counter[0] (offset by the grid size),
@@ -483,13 +538,8 @@ __device__ __forceinline__ void zstage_item(const ZArgs& a, int it, float2* lds)
   const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
   v4f acc[T][CB];
   restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
-  ZTwiddles<T> Z;
-  Z.load(a.roots);
-  for (int s = 0; s < a.nrhs; ++s) {
-    float2* Hs = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq);
-    zfft_rhs<T, CB>(acc, Hs, a.nq, 1, q0 + w * CB * 16, a.nq, Z);
-  }
-  __syncthreads();
+  (void)w;
+  zstage_pencils<T, CB>(acc, a, pl, q0, lds);
 }
 
 // The first item of every block is its own index; only a launch with more
