@@ -532,13 +532,11 @@ __device__ __forceinline__ void leave_queue(const ZArgs& a) {
 template <int FMT, int T, int CB, bool BF>
 __device__ __forceinline__ void zstage_item(const ZArgs& a, int it, float2* lds) {
   constexpr int NW = 4, QT = 16 * CB * NW;
-  const int w = threadIdx.x >> 6;
   const int ntile = a.nq / QT;
   const int pl = it / ntile, q0 = (it - pl * ntile) * QT;
   const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
   v4f acc[T][CB];
   restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
-  (void)w;
   zstage_pencils<T, CB>(acc, a, pl, q0, lds);
 }
 

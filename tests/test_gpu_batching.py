@@ -192,3 +192,42 @@ def test_persistent_queue_path_matches_oracle(fmt):
         assert O.rel_l2(got[0, p], ref[0, p]) < 1e-4
     op.release()
     ctx.close()
+
+
+@pytest.mark.parametrize("fmt,K", [("tt3d", (24, 24, 24)), ("full", (12, 12, 12))])
+def test_direction_chunking_invariance(fmt, K):
+    """The three-pass pipeline splits the directions into chunks whose half
+    spectrum fits the scratch cap (TFMM_HCAP_MB).  Each direction's arithmetic is
+    the same whatever the chunk, so one chunk per direction and a single chunk for
+    all directions must agree bit for bit, and both match the oracle."""
+    import paper_2010_00520_amd as P
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L = 3
+    ndir, (rk, data, comp) = _factors(fmt, K, L)
+    A_np = synth.gaussian_patterns((2, ndir) + K, 37)
+    A = torch.from_numpy(A_np).cuda()
+    outs = {}
+    for cap in ("1", "4096"):
+        old = os.environ.get("TFMM_HCAP_MB")
+        os.environ["TFMM_HCAP_MB"] = cap
+        os.environ["TFMM_NO_FUSED"] = "1"
+        try:
+            ctx = P.Context(0)
+        finally:
+            os.environ.pop("TFMM_NO_FUSED", None)
+            if old is None:
+                os.environ.pop("TFMM_HCAP_MB", None)
+            else:
+                os.environ["TFMM_HCAP_MB"] = old
+        op = ctx.import_factors(K, L, fmt, rk, data)
+        B = torch.zeros_like(A)
+        ctx.translate(op, A, B)
+        torch.cuda.synchronize()
+        outs[cap] = B.cpu()
+        op.release()
+        ctx.close()
+    assert torch.equal(outs["1"], outs["4096"])
+    got = outs["1"].numpy().astype(np.complex128)
+    assert O.rel_l2(got, O.translate_compressed(A_np, comp)) < 2e-5
