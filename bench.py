@@ -408,6 +408,18 @@ def main():
             res[prec] = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": op.ranks(), "setup_s": setup_s,
                          "plan": op.plan(), "autotune": tuned, "B": B.cpu().numpy().astype(np.complex128)}
             op.release()
+        # the batching grid is also run with Tucker-4D (per-call core contraction
+        # + register-chained restoration, the format with the smallest operator there)
+        extra = {}
+        for xf in (["tucker4d"] if args.workload == "batching" and not args.fmt else []):
+            t0 = time.perf_counter()
+            op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=xf, tol=w.tol, prec=precs[0])
+            setup_s = time.perf_counter() - t0
+            ctx.autotune(op, nrhs=w.nrhs, reps=10)
+            B = torch.zeros_like(A)
+            ms_x, lat_x, kt_x = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
+            extra[xf] = {"ms": ms_x, "kt": kt_x, "info": op.info(), "setup_s": setup_s, "plan": op.plan()}
+            op.release()
         full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
         if args.autotune or args.workload == "batching":
             ctx.autotune(full, nrhs=w.nrhs, reps=10)
@@ -497,6 +509,14 @@ def main():
                      "p50_ms": float(np.percentile(q["lat"], 50)), "p99_ms": float(np.percentile(q["lat"], 99)),
                      "time_ratio_compressed_over_full": q["ms"] / ms_f, "kernels": q["kt"],
                      "roofline": roofline(prec, q)}
+    if extra:
+        out["other_formats"] = {
+            xf: {"precision": precs[0], "value": units / (x["ms"] * 1e-3), "ms_per_step": x["ms"],
+                 "time_ratio_compressed_over_full": x["ms"] / ms_f,
+                 "memory_fraction": x["info"]["bytes_stored"] / finfo["bytes_stored"],
+                 "ranks": x["info"]["ranks"], "rel_err_fro": x["info"]["rel_err_fro"], "setup_s": x["setup_s"],
+                 "plan": x["plan"], "kernels": x["kt"]}
+            for xf, x in extra.items()}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, fmt, {p: res[p]["B"] for p in precs}, A_np, args.cpu_seconds)
         out["rel_err_vs_fp64"] = out["cpu_baseline"]["gpu_rel_err_max"][head]
