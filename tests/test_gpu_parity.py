@@ -264,3 +264,47 @@ def test_unsupported_grids_rejected(ctx):
         with pytest.raises(P.TfmmError) as e:
             ctx.setup(K=K, box=0.5, L=3, fmt="full")
         assert e.value.status == 2, K
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("no_fused", ["0", "1"])
+@pytest.mark.parametrize("fmt", ["tucker3d", "tucker4d", "htucker4d"])
+def test_lds_staged_tucker_restoration(fmt, no_fused, prec):
+    """The Tucker family's LDS-staged restoration (block GEMMs through LDS, used
+    when a chunk of the register-chained one does not fit; TFMM_NO_TK2=1 forces
+    it) against the oracle, on the fused and the three-pass paths."""
+    import os
+
+    import paper_2010_00520_amd as P
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    K, L = (16, 16, 16), 3
+    n = tuple(2 * k for k in K)
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(seed_of("staged", fmt))
+    ranks = {"tucker4d": (9, 11, 7, 13), "htucker4d": (8, 9, 7, 10, 12, 11)}.get(fmt)
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    old = {k: os.environ.get(k) for k in ("TFMM_NO_TK2", "TFMM_NO_FUSED")}
+    os.environ["TFMM_NO_TK2"] = "1"
+    os.environ["TFMM_NO_FUSED"] = no_fused
+    try:
+        c = P.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    op = c.import_factors(K, L, fmt, rk, data, prec=prec)
+    plan = op.plan()
+    assert not plan["register_chained"] and plan["fused"] == (no_fused == "0")
+    A = synth.gaussian_patterns((2, ndir) + K, 38)
+    ref = O.translate_compressed(A, comp)
+    got = gpu_translate(c, op, A)
+    tol = 1e-4 if prec == "bf16x3" else ARITH_TOL
+    assert O.rel_l2(got, ref) < tol
+    for p in (0, ndir // 2, ndir - 1):
+        assert O.rel_l2(got[:, p], ref[:, p]) < 5 * tol
+    op.release()
+    c.close()
