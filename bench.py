@@ -97,22 +97,27 @@ def fft_flops(K, n, ndir, nrhs):
 
 def time_steps(ctx, op, A, B, steps, warmup, torch):
     """Time `steps` translations as the library runs them (a captured hipGraph per
-    (op, nrhs, A, B) replayed on torch's current stream), then, in a separate
-    eager pass with the library's HIP-event profiling on, the per-kernel durations
-    on the stream the kernels are launched on."""
+    (op, nrhs, A, B) replayed on torch's current stream) between two
+    synchronisations; then per-step latencies from HIP events around each step
+    in a pass of their own (an event pair costs GPU time of its own, so it stays
+    out of the timed loop); then, in an eager pass with the library's HIP-event
+    profiling on, the per-kernel durations on the stream the kernels run on."""
     st = torch.cuda.current_stream()
     for _ in range(warmup):
         ctx.translate(op, A, B)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(steps):
+    for _ in range(steps):
+        ctx.translate(op, A, B)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nl = min(steps, 200)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
+    for i in range(nl):
         evs[i][0].record(st)
         ctx.translate(op, A, B)
         evs[i][1].record(st)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     ctx.set_profiling(True)
     ctx.kernel_times(reset=True)
