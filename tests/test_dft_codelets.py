@@ -45,7 +45,8 @@ int main() {
     if (!ok) {
       switch (n) {
 #define SCASE(N) case N: if (kind[1]=='F') dft_full_fwd_##N(x, y); else dft_full_inv_##N(x, y); break;
-        SCASE(1) SCASE(2) SCASE(3) SCASE(4) SCASE(5) SCASE(6) SCASE(7) SCASE(8) SCASE(16)
+        SCASE(1) SCASE(2) SCASE(3) SCASE(4) SCASE(5) SCASE(6) SCASE(7) SCASE(8) SCASE(12) SCASE(16) SCASE(24)
+        SCASE(32)
       }
       nout = n;
     }
@@ -90,9 +91,32 @@ def test_pruned_codelets_match_numpy(codelet_exe, n):
     assert np.linalg.norm(yi - refi) / np.linalg.norm(refi) < 2e-7
 
 
-@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8, 16])
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32])
 def test_full_codelets_match_numpy(codelet_exe, t):
     rng = np.random.default_rng(100 + t)
     x = (rng.standard_normal(t) + 1j * rng.standard_normal(t)).astype(np.complex64)
-    np.testing.assert_allclose(_run(codelet_exe, "fF", t, x), np.fft.fft(x.astype(np.complex128)), atol=2e-6)
-    np.testing.assert_allclose(_run(codelet_exe, "iI", t, x), np.fft.ifft(x.astype(np.complex128)) * t, atol=2e-6)
+    ref = np.fft.fft(x.astype(np.complex128))
+    assert np.linalg.norm(_run(codelet_exe, "fF", t, x) - ref) / np.linalg.norm(ref) < 2e-7
+    refi = np.fft.ifft(x.astype(np.complex128)) * t
+    assert np.linalg.norm(_run(codelet_exe, "iI", t, x) - refi) / np.linalg.norm(refi) < 2e-7
+
+
+@pytest.mark.parametrize("n3", [8, 16, 24, 32, 48, 64])
+def test_even_odd_split_of_the_pruned_z_transform(codelet_exe, n3):
+    """The three-pass z-stage's pencil transform, in the codelets' own arithmetic:
+    X[2m] = DFT_K(x)[m], X[2m+1] = DFT_K(x w^z)[m] (K = n3/2 nonzero inputs), then
+    y[z] = IDFT_K(P_even)[z] + w^-z IDFT_K(P_odd)[z] for z < K, against the pruned
+    transform pair written out with numpy."""
+    K = n3 // 2
+    rng = np.random.default_rng(300 + n3)
+    x = (rng.standard_normal(K) + 1j * rng.standard_normal(K)).astype(np.complex64)
+    t = (rng.standard_normal(n3) + 1j * rng.standard_normal(n3)).astype(np.complex64)
+    w = np.exp(-2j * np.pi * np.arange(K) / n3)
+    E = _run(codelet_exe, "fF", K, x)
+    O = _run(codelet_exe, "fF", K, (x * w).astype(np.complex64))
+    ye = _run(codelet_exe, "iI", K, (E * t[0::2]).astype(np.complex64))
+    yo = _run(codelet_exe, "iI", K, (O * t[1::2]).astype(np.complex64))
+    y = ye + np.conj(w) * yo
+    X = np.fft.fft(np.concatenate([x.astype(np.complex128), np.zeros(K)]))
+    ref = (np.fft.ifft(X * t.astype(np.complex128)) * n3)[:K]
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 1e-6
