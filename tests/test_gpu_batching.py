@@ -51,7 +51,7 @@ def _factors(fmt, K, L):
     n = tuple(2 * k for k in K)
     ndir = (L + 1) * 2 * (L + 1)
     rng = np.random.default_rng(4321)
-    ranks = {"htucker4d": (6, 5, 4, 7, 10, 9)}.get(fmt)
+    ranks = {"htucker4d": (6, 5, 4, 7, 10, 9), "tt4d": (5, 6, 7)}.get(fmt)
     return ndir, random_factors(fmt, n, ndir, rng, ranks)
 
 
@@ -194,7 +194,7 @@ def test_persistent_queue_path_matches_oracle(fmt):
     ctx.close()
 
 
-@pytest.mark.parametrize("fmt,K", [("tt3d", (24, 24, 24)), ("full", (12, 12, 12))])
+@pytest.mark.parametrize("fmt,K", [("tt3d", (24, 24, 24)), ("full", (12, 12, 12)), ("tt4d", (16, 16, 8))])
 def test_direction_chunking_invariance(fmt, K):
     """The three-pass pipeline splits the directions into chunks whose half
     spectrum fits the scratch cap (TFMM_HCAP_MB).  Each direction's arithmetic is
@@ -204,7 +204,7 @@ def test_direction_chunking_invariance(fmt, K):
 
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    L = 3
+    L = 2
     ndir, (rk, data, comp) = _factors(fmt, K, L)
     A_np = synth.gaussian_patterns((2, ndir) + K, 37)
     A = torch.from_numpy(A_np).cuda()
