@@ -634,11 +634,20 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   const int rhs_group = std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH);
   int ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, hcap / (per_dir_rhs * rhs_group)));
   const size_t hbytes = op->fused ? 0 : per_dir_rhs * rhs_group * ndl;
+  // three-pass: A and B go through z-major copies (a z-slab of a box block is
+  // then contiguous for the xy passes; in the caller's layout it is strided by
+  // K3).  Measured faster for K3 = 8 and 16 (e.g. 256x16x16: xy passes 258 ->
+  // 227 us per launch with the copies), slower for K3 = 24 and 32.
+  const long long box = (long long)op->K[0] * op->K[1] * K3;
+  const bool zm = !op->fused && K3 >= 8 && K3 <= 16;
+  const size_t zbytes = zm ? (size_t)box * rhs_group * ndl * sizeof(float2) : 0;
+  const size_t a1b = (op->a1_bytes + 255) / 256 * 256;
   void* scr = nullptr;
-  tfmm_status s = ensure_scratch(c, slot, hbytes + op->a1_bytes, &scr);
+  tfmm_status s = ensure_scratch(c, slot, hbytes + a1b + zbytes, &scr);
   if (s != TFMM_OK) return s;
   float2* H = (float2*)scr;
   float2* a1 = (float2*)((char*)scr + hbytes);
+  float2* Zs = (float2*)((char*)scr + hbytes + a1b);
   if (op->a1_bytes) {
     s = run_a1(c, op, a1, st);
     if (s != TFMM_OK) return s;
@@ -704,9 +713,22 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
     for (int p0 = 0; p0 < nd; p0 += ndl) {
       const int nl = std::min(ndl, nd - p0);
       bool ok = false;
+      tfmm::RhsPtrs PZ{};
+      if (zm) {
+        for (int i = 0; i < nr; ++i) {
+          PZ.a[i] = Zs + (long long)i * nl * box;
+          PZ.b[i] = Zs + (long long)i * nl * box;
+        }
+        Launch L(c, st, "box_to_zmajor");
+        HIP_TRY(tfmm::launch_box_zmajor(true, P, Zs, op->K[0], op->K[1], K3, nr, p0, nl, op->d_perm, st));
+        L.done();
+      }
       {
         Launch L(c, st, "fwd_xy");
-        HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, twx, st, &ok));
+        if (zm)
+          HIP_TRY(tfmm::launch_fwd_xy(PZ, H, n1, n2, K3, nr, 0, nl, nullptr, twx, st, &ok, true));
+        else
+          HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, twx, st, &ok));
         L.done();
       }
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "xy-FFT sizes unsupported");
@@ -721,7 +743,15 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "z-stage size unsupported");
       {
         Launch L(c, st, "inv_xy");
-        HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, scale, twx, st, &ok));
+        if (zm)
+          HIP_TRY(tfmm::launch_inv_xy(PZ, H, n1, n2, K3, nr, 0, nl, nullptr, scale, twx, st, &ok, true));
+        else
+          HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, scale, twx, st, &ok));
+        L.done();
+      }
+      if (zm) {
+        Launch L(c, st, "zmajor_to_box");
+        HIP_TRY(tfmm::launch_box_zmajor(false, P, Zs, op->K[0], op->K[1], K3, nr, p0, nl, op->d_perm, st));
         L.done();
       }
     }

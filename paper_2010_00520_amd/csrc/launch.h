@@ -61,10 +61,17 @@ struct RhsPtrs {
 // xy passes of the three-pass pipeline.  n1 in {8,...,64, 128, 256}, n2 <= 64;
 // twx = exp(-2 pi i m / n1), m < n1, is read only when n1 > 64.
 // Direction p0 + d of the launch is perm[p0 + d] (perm NULL: p0 + d).
+// zm: A (forward) / B (inverse) are z-major staged copies (see launch_box_zmajor).
 hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const int* perm, const float2* twx, hipStream_t st, bool* supported);
+                         const int* perm, const float2* twx, hipStream_t st, bool* supported, bool zm = false);
 hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported);
+                         const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported,
+                         bool zm = false);
+// Box blocks of the launch (RHS s < nrhs, directions perm[p0 + d], d < ndl) to
+// (to_z: from P.a) or from (P.b) their z-major copies at Z + (s*ndl + d)*K1*K2*K3,
+// element (x, y, z) at (z*K1 + x)*K2 + y.  K3 <= 64.
+hipError_t launch_box_zmajor(bool to_z, const RhsPtrs& P, float2* Z, int K1, int K2, int K3, int nrhs, int p0,
+                             int ndl, const int* perm, hipStream_t st);
 // Zero n ints (a kernel, so that it may be captured in a graph).
 hipError_t launch_zero(int* p, int n, hipStream_t st);
 hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported);

@@ -31,16 +31,24 @@ __device__ __forceinline__ void dft_full_inv_nb(const float2* x, float2* y) {
   else dft_full_inv_16(x, y);
 }
 
+// Element (x, y, z) of a box block: caller layout [x][y][z] (z fastest), or,
+// with zm set, z-major [z][x][y] (the three-pass pipeline's staged copy, so a
+// block's z-slab is contiguous).
+template <int K1, int K2>
+__device__ __forceinline__ long long box_at(int x, int y, int z, int K3, bool zm) {
+  return zm ? ((long long)z * K1 + x) * K2 + y : ((long long)x * K2 + y) * K3 + z;
+}
+
 template <int N1, int N2, int NT>
 __device__ __forceinline__ void xy_forward(float2* lds, const float2* __restrict__ Ab, int K3, int zg, int zp,
-                                           int z0, const float2* __restrict__ twx) {
+                                           int z0, const float2* __restrict__ twx, bool zm = false) {
   constexpr int K1 = N1 / 2, K2 = N2 / 2;
   if constexpr (N1 <= 64) {
     for (int task = threadIdx.x; task < K2 * zg; task += NT) {
       const int z = task % zg, y = task / zg;
       float2 x[K1], X[N1];
 #pragma unroll
-      for (int i = 0; i < K1; ++i) x[i] = Ab[((long long)i * K2 + y) * K3 + z0 + z];
+      for (int i = 0; i < K1; ++i) x[i] = Ab[box_at<K1, K2>(i, y, z0 + z, K3, zm)];
       Dft<N1>::fwd(x, X);
 #pragma unroll
       for (int f = 0; f < N1; ++f) lds[(f * N2 + y) * zp + z] = X[f];
@@ -51,7 +59,7 @@ __device__ __forceinline__ void xy_forward(float2* lds, const float2* __restrict
       const int z = task % zg, r = task / zg, y = r % K2, j2 = r / K2;
       float2 a[NA / 2], Y[NA];
 #pragma unroll
-      for (int j1 = 0; j1 < NA / 2; ++j1) a[j1] = Ab[((long long)(NB * j1 + j2) * K2 + y) * K3 + z0 + z];
+      for (int j1 = 0; j1 < NA / 2; ++j1) a[j1] = Ab[box_at<K1, K2>(NB * j1 + j2, y, z0 + z, K3, zm)];
       Dft<NA>::fwd(a, Y);
 #pragma unroll
       for (int k1 = 0; k1 < NA; ++k1) lds[((k1 + NA * j2) * N2 + y) * zp + z] = cmul(Y[k1], twx[j2 * k1]);
@@ -81,7 +89,7 @@ __device__ __forceinline__ void xy_forward(float2* lds, const float2* __restrict
 
 template <int N1, int N2, int NT>
 __device__ __forceinline__ void xy_inverse(float2* lds, float2* __restrict__ Bb, int K3, int zg, int zp, int z0,
-                                           float scale, const float2* __restrict__ twx) {
+                                           float scale, const float2* __restrict__ twx, bool zm = false) {
   constexpr int K1 = N1 / 2, K2 = N2 / 2;
   for (int task = threadIdx.x; task < N1 * zg; task += NT) {
     const int z = task % zg, fx = task / zg;
@@ -101,7 +109,7 @@ __device__ __forceinline__ void xy_inverse(float2* lds, float2* __restrict__ Bb,
       for (int i = 0; i < N1; ++i) x[i] = lds[(i * N2 + y) * zp + z];
       Dft<N1>::inv(x, X);
 #pragma unroll
-      for (int i = 0; i < K1; ++i) Bb[((long long)i * K2 + y) * K3 + z0 + z] = cscale(X[i], scale);
+      for (int i = 0; i < K1; ++i) Bb[box_at<K1, K2>(i, y, z0 + z, K3, zm)] = cscale(X[i], scale);
     }
   } else {
     constexpr int NA = 16, NB = N1 / 16;
@@ -123,7 +131,7 @@ __device__ __forceinline__ void xy_inverse(float2* lds, float2* __restrict__ Bb,
       Dft<NA>::inv(c, xo);
 #pragma unroll
       for (int j1 = 0; j1 < NA / 2; ++j1)
-        Bb[((long long)(NB * j1 + j2) * K2 + y) * K3 + z0 + z] = cscale(xo[j1], scale);
+        Bb[box_at<K1, K2>(NB * j1 + j2, y, z0 + z, K3, zm)] = cscale(xo[j1], scale);
     }
   }
 }
