@@ -136,7 +136,8 @@ typedef struct {
  *   TFMM_NO_TK2=1    restore Tucker-family operators through LDS-staged
  *                    products instead of the register-chained restoration;
  *   TFMM_HCAP_MB=n   bytes (MiB) of the three-pass pipeline's half-spectrum
- *                    scratch per chunk of directions (default 256);
+ *                    scratch per chunk of directions (default: an eighth of
+ *                    the budget, within 64 MiB .. 1 GiB);
  *   TFMM_GRAPH=0|1   never / always replay tfmm_translate from a captured
  *                    hipGraph (default: only multi-launch translations). */
 tfmm_status tfmm_ctx_create(int device, size_t hbm_budget_bytes, tfmm_ctx* out);
