@@ -145,8 +145,23 @@ def near_mask(D: np.ndarray, rule: str = "cheb", param: float = 1.0) -> np.ndarr
 
 
 def hankel2(l, x):
-    """Spherical Hankel function of the second kind, h_l^(2) = j_l - i y_l (R3)."""
-    return special.spherical_jn(l, x) - 1j * special.spherical_yn(l, x)
+    """Spherical Hankel function of the second kind, h_l^(2) = j_l - i y_l (R3).
+
+    Real x: the library's j_l and y_l.  Complex x (a lossy medium, Section
+    III-A-5, has a complex wavenumber): j_l and y_l both grow like e^{|Im x|}
+    while h_l^(2) decays like e^{-|Im x|} for Im x < 0, so their difference
+    cancels; the finite closed form of h_l^(2) (DLMF section 10.49(i)) is summed
+    instead: h_l^(2)(x) = e^{-ix} sum_{k=0}^{l} (-i)^{k-l-1} a_k / x^{k+1},
+    a_k = (l+k)! / (2^k k! (l-k)!).
+    """
+    if not np.iscomplexobj(x):
+        return special.spherical_jn(l, x) - 1j * special.spherical_yn(l, x)
+    x = np.asarray(x, dtype=np.complex128)
+    total = np.zeros_like(x)
+    for k in range(l + 1):
+        a_k = math.factorial(l + k) / (2.0 ** k * math.factorial(k) * math.factorial(l - k))
+        total = total + ((-1j) ** (k - l - 1)) * a_k / x ** (k + 1)
+    return np.exp(-1j * x) * total
 
 
 def legendre(l, t):
@@ -154,10 +169,11 @@ def legendre(l, t):
     return special.eval_legendre(l, t)
 
 
-def operator_value(khat: np.ndarray, R: np.ndarray, k: float, L: int, scale: complex = 1.0):
+def operator_value(khat: np.ndarray, R: np.ndarray, k, L: int, scale: complex = 1.0):
     """T_L(khat, R) = scale * sum_{l=0}^{L} (-i)^l (2l+1) h_l^(2)(k|R|) P_l(khat . Rhat).
 
     khat: (..., 3) unit vectors, R: (..., 3) nonzero separations; broadcast together.
+    k: real, or complex with Im k < 0 in a lossy medium (Section III-A-5).
     """
     khat = np.asarray(khat, dtype=np.float64)
     R = np.asarray(R, dtype=np.float64)

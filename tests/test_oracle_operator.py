@@ -154,3 +154,64 @@ def test_direction_mode_rank_is_spherical_degree():
     s = np.linalg.svd(Th.reshape(Th.shape[0], -1), compute_uv=False)
     r = int(np.sum(s > 1e-11 * s[0]))
     assert r == (L + 1) ** 2
+
+
+# Relative permittivities of the lossy-medium test (Table IV); k = k0 sqrt(eps_r),
+# Im k < 0 under the e^{jwt} convention of Section II-A.
+LOSSY_EPS = (2 - 1j, 2 - 2j, 2 - 8j)
+
+
+def test_hankel_complex_argument():
+    """h_l^(2) at complex arguments (Section III-A-5).  Where the loss is mild the
+    oracle's finite sum agrees with the library's j_l - i y_l (an independent
+    route); where it is strong (|Im x| up to 90, j_l and y_l ~ e^{90}) it still
+    satisfies the closed forms of h_0, h_1 and the three-term recurrence
+    h_{l-1} + h_{l+1} = (2l+1)/x h_l (DLMF 10.51.1) to rounding."""
+    from scipy import special
+
+    z = np.array([1.0, 3.3, 6.28, 12.0]) * np.sqrt(2 - 1j)
+    for l in range(15):
+        ref = special.spherical_jn(l, z) - 1j * special.spherical_yn(l, z)
+        np.testing.assert_allclose(O.hankel2(l, z), ref, rtol=1e-11)
+    z = np.array([1.0, 3.3, 6.28, 12.0, 40.0]) * np.sqrt(2 - 8j)
+    np.testing.assert_allclose(O.hankel2(0, z), 1j * np.exp(-1j * z) / z, rtol=1e-14)
+    np.testing.assert_allclose(O.hankel2(1, z), np.exp(-1j * z) * (1j / z ** 2 - 1 / z), rtol=1e-13)
+    for l in range(1, 15):
+        lhs = O.hankel2(l - 1, z) + O.hankel2(l + 1, z)
+        np.testing.assert_allclose(lhs, (2 * l + 1) / z * O.hankel2(l, z), rtol=1e-13)
+    # the real-axis limit of the complex route is the real route
+    x = np.array([0.7, 3.3, 12.0])
+    for l in (0, 5, 14):
+        np.testing.assert_allclose(O.hankel2(l, x + 0j), O.hankel2(l, x), rtol=1e-12)
+
+
+@pytest.mark.parametrize("eps", LOSSY_EPS)
+def test_addition_theorem_lossy_medium(eps):
+    """Eq. (7) with a complex wavenumber still reproduces the decaying Green's function
+    exp(-jk|X+d|)/|X+d| through the plane-wave expansion, with an error that falls as L
+    grows (L = 10 -> 18: 2.7e-4 -> 3.5e-7, 1.8e-3 -> 1.7e-6, 1.7 -> 9.5e-4 for the three
+    permittivities)."""
+    k = 2 * math.pi * np.sqrt(complex(eps))
+    a = 0.5
+    rng = np.random.default_rng(7)
+    Xs = [np.array([2, 2, 0.0]) * a, np.array([3, -2, 2.0]) * a, np.array([2, 0, 0.0]) * a]
+    ds = [rng.uniform(-a / 2, a / 2, 3) - rng.uniform(-a / 2, a / 2, 3) for _ in range(4)]
+    e10 = max(_addition_error(10, X, d, k) for X in Xs for d in ds)
+    e18 = max(_addition_error(18, X, d, k) for X in Xs for d in ds)
+    assert e18 < 2e-3
+    assert e18 < e10 / 100
+
+
+def test_loss_lowers_ranks_and_memory():
+    """Table IV and Section III-A-5: the loss of the medium lowers the ranks, so the
+    memory of the compressed operator falls as the permittivity's imaginary part grows
+    (6^3 boxes, 0.5 wavelength, L = 8, gamma = 1e-4)."""
+    khat, _ = O.directions(8)
+    stored = {}
+    for eps in (2,) + LOSSY_EPS:
+        k = 2 * math.pi * np.sqrt(complex(eps))
+        Th = O.fft_operator(O.sample_operator((6, 6, 6), 0.5, k, 8, khat))
+        stored[eps] = {f: O.stored_elements(O.compress(Th, f, 1e-4)) for f in ("htucker4d", "tt4d")}
+    for f in ("htucker4d", "tt4d"):
+        seq = [stored[e][f] for e in (2,) + LOSSY_EPS]
+        assert all(b < a for a, b in zip(seq, seq[1:])), (f, seq)
