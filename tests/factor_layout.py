@@ -84,3 +84,48 @@ def oracle_to_layout(comp, n, ndir):
                                                                  comp["B"].ravel()])
         return [r1, r2, r3, r4, r12, r34], data
     raise ValueError(fmt)
+
+
+def layout_to_oracle(fmt, ranks, data, n, ndir):
+    """Import/export layout (ranks, complex128 data) -> the oracle's compressed-operator dict.
+
+    The inverse of oracle_to_layout: slices and reshapes only."""
+    n1, n2, n3 = n
+    data = np.asarray(data, dtype=np.complex128).ravel()
+    pos = [0]
+
+    def take(shape):
+        m = int(np.prod(shape))
+        a = data[pos[0]:pos[0] + m].reshape(shape)
+        pos[0] += m
+        return a
+
+    if fmt == "full":
+        comp = {"fmt": fmt, "T": take((ndir, n1, n2, n3))}
+    elif fmt == "tucker3d":
+        r = np.asarray(ranks).reshape(ndir, 3)
+        per = []
+        for r1, r2, r3 in r:
+            C = take((r1, r2, r3))
+            per.append((C, [take((n1, r1)), take((n2, r2)), take((n3, r3))]))
+        comp = {"fmt": fmt, "per": per}
+    elif fmt == "tt3d":
+        r = np.asarray(ranks).reshape(ndir, 2)
+        comp = {"fmt": fmt, "per": [(take((n1, r1)), take((r1, n2, r2)), take((n3, r2))) for r1, r2 in r]}
+    elif fmt == "tucker4d":
+        r1, r2, r3, r4 = ranks
+        C = take((r1, r2, r3, r4))
+        comp = {"fmt": fmt, "C": C, "U": [take((n1, r1)), take((n2, r2)), take((n3, r3)), take((ndir, r4))]}
+    elif fmt == "tt4d":
+        r1, r2, r3 = ranks
+        comp = {"fmt": fmt, "U1": take((n1, r1)), "C1": take((r1, n2, r2)), "C2": take((r2, n3, r3)),
+                "U3": take((ndir, r3))}
+    elif fmt == "htucker4d":
+        r1, r2, r3, r4, r12, r34 = ranks
+        Us = [take((n1, r1)), take((n2, r2)), take((n3, r3)), take((ndir, r4))]
+        comp = {"fmt": fmt, "U": Us, "C12": take((r1, r2, r12)), "C34": take((r3, r4, r34)), "B": take((r12, r34))}
+    else:
+        raise ValueError(fmt)
+    if pos[0] != data.size:
+        raise ValueError(f"layout holds {data.size} entries, ranks account for {pos[0]}")
+    return comp

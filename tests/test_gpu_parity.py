@@ -308,3 +308,26 @@ def test_lds_staged_tucker_restoration(fmt, no_fused, prec):
         assert O.rel_l2(got[:, p], ref[:, p]) < 5 * tol
     op.release()
     c.close()
+
+
+@pytest.mark.parametrize("K,L", [((4, 4, 4), 5), ((64, 4, 4), 14)])
+def test_fp64_sampler_matches_oracle(ctx, K, L):
+    """FP64 operator sampling on the device (Eq. (7), readings R1-R3), then the host
+    FP64 FFT: the uncompressed operator read back with tfmm_op_export must match the
+    oracle's sampled and FFT'ed operator to 1e-12 relative (the FP64 rounding level of
+    the spherical-Hankel and Legendre recurrences), and its inverse FFT the spatial
+    samples, both per direction.  64 x 4 x 4 boxes at L = 14 reach l > kR for every
+    offset, where an unstable recurrence for h_l would show."""
+    w = synth.TINY.with_(K=K, L=L)
+    op = ctx.setup(K=K, box=w.box, k=w.k, L=L, fmt="full")
+    n = tuple(2 * k for k in K)
+    got = op.export().reshape((w.n_dir,) + n)
+    op.release()
+    khat, _ = O.directions(L)
+    T = O.sample_operator(K, w.box, w.k, L, khat)
+    That = O.fft_operator(T)
+    assert O.rel_l2(got, That) <= 1e-12
+    spatial = np.fft.ifftn(got, axes=(-3, -2, -1))
+    for p in range(w.n_dir):
+        assert O.rel_l2(got[p], That[p]) <= 1e-12, p
+        assert O.rel_l2(spatial[p], T[p]) <= 1e-12, p

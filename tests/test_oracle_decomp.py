@@ -225,3 +225,22 @@ def test_table2_ranks_soft_pin():
     assert ht[4] == ht[5]
     assert abs(ht[4] - g["htucker_r12"]) <= 3
     assert abs(max(ht[:3]) - g["htucker_leaf"]) <= 4
+
+
+def test_stored_elements_counts_cores_and_factors():
+    """Section III-A: the memory of a compressed operator is that of its core tensors
+    and factor matrices.  A separable operator (every T~_p an outer product, the
+    direction mode a vector too) compresses to rank 1 in every format, so the counts
+    follow from the mode sizes (8, 6, 4) and 3 directions, written out by hand:
+    Tucker-3D 3 x (1 + 8 + 6 + 4), TT-3D 3 x (8 + 6 + 4), Tucker-4D 1 + 8 + 6 + 4 + 3,
+    TT-4D 8 + 6 + 4 + 3, H-Tucker leaves 8 + 6 + 4 + 3 plus two transfer tensors and
+    the root of one entry each, uncompressed 3 x 8 x 6 x 4."""
+    rng = _rng(11)
+    a, b, c, d = (_rand((m,), rng) for m in (8, 6, 4, 3))
+    That = np.einsum("p,x,y,z->pxyz", d, a, b, c)
+    expect = {"full": 576, "tucker3d": 57, "tt3d": 54, "tucker4d": 22, "tt4d": 21, "htucker4d": 24}
+    for fmt, count in expect.items():
+        comp = O.compress(That, fmt, 1e-10)
+        assert O.stored_elements(comp) == count, fmt
+        # and the compressed form is exact (rank 1 holds the whole tensor)
+        assert O.rel_l2(O.restore_all(comp, 3), That) < 1e-12, fmt
