@@ -39,20 +39,21 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0  # dense
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=40)
-    ap.add_argument("--workload", default="plain", choices=["plain", "batching", "precision", "tiny", "serving"])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batching",
+                    choices=["batching", "plain", "precision", "tiny", "serving"])
     ap.add_argument("--requests", type=int, default=2000, help="serving: number of requests in the stream")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run 10 plain device copies of MIB MiB (reference for HBM byte counters)")
-    ap.add_argument("--fmt", default=None, help="override the compressed format")
+    ap.add_argument("--fmt", default=None, help="override the headline compressed format")
     ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3"],
-                    help="override the restoration arithmetic")
-    ap.add_argument("--autotune", action="store_true",
-                    help="run tfmm_autotune for the workload's RHS count before timing "
-                         "(always on for the batching and precision workloads)")
+                    help="time only this restoration arithmetic")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the side formats and the summaries of the other workloads")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-leg", action="store_true", help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -61,38 +62,93 @@ def workload(name):
             "tiny": synth.TINY}[name]
 
 
-def restore_flops(fmt, ranks, n, ndir):
-    """Real flops of the restoration contractions per launch (8 per complex MAC), shared over RHS."""
+# headline format of each workload and the formats timed beside it
+HEADLINE = {"batching": ("tucker4d", ("tt3d",)), "plain": ("tucker3d", ()),
+            "precision": ("htucker4d", ("tt4d",)), "tiny": ("tucker3d", ())}
+METRIC = "translated grid-pts\u00d7dirs/s compressed vs uncompressed at rel err\u22641e-4; p99 lat"
+
+
+def restore_macs(fmt, ranks, n, ndir):
+    """Complex multiply-adds of the restoration per launch, shared over RHS:
+    (a1: per-direction cores / TT slices of the 4-D formats, a2: factor-by-core
+    reconstruction of every T~_p), the orders of Figs. 3-4."""
     n1, n2, n3 = n
     N = n1 * n2 * n3
-    cm = 0
+    a1 = a2 = 0
     if fmt == "tucker3d":
-        r = np.asarray(ranks).reshape(-1, 3)
-        for r1, r2, r3 in r:
-            cm += n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3
+        for r1, r2, r3 in np.asarray(ranks).reshape(-1, 3):
+            a2 += n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3
     elif fmt == "tt3d":
-        r = np.asarray(ranks).reshape(-1, 2)
-        for r1, r2 in r:
-            cm += n1 * r1 * n2 * r2 + N * r2
+        for r1, r2 in np.asarray(ranks).reshape(-1, 2):
+            a2 += n1 * r1 * n2 * r2 + N * r2
     elif fmt == "tucker4d":
-        r1, r2, r3, r4 = ranks
-        cm += ndir * (r1 * r2 * r3 * r4 + n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3)
+        r1, r2, r3, r4 = ranks[:4]
+        a1 = ndir * r1 * r2 * r3 * r4
+        a2 = ndir * (n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3)
     elif fmt == "htucker4d":
-        r1, r2, r3, r4, r12, r34 = ranks
-        cm += ndir * (r3 * r4 * r34 + r3 * r34 * r12 + r1 * r2 * r12 * r3 + n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3
-                      + N * r3)
+        r1, r2, r3, r4, r12, r34 = ranks[:6]
+        a1 = ndir * (r3 * r4 * r34 + r3 * r34 * r12 + r1 * r2 * r12 * r3)
+        a2 = ndir * (n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3)
     elif fmt == "tt4d":
-        r1, r2, r3 = ranks
-        cm += n1 * r1 * n2 * r2 + ndir * (r2 * n3 * r3 + N * r2)
-    return 8.0 * cm
+        r1, r2, r3 = ranks[:3]
+        a1 = n1 * r1 * n2 * r2 + ndir * r2 * n3 * r3
+        a2 = ndir * N * r2
+    return int(a1), int(a2)
 
 
 def fft_flops(K, n, ndir, nrhs):
-    """Real flops of the pruned forward + inverse 3-D FFTs (5 m log2 m per line of length m)."""
+    """Real flops of the pruned forward + inverse 3-D FFTs (5 m log2 m per line of
+    length m) and the pointwise product (6 per complex element), split into the
+    x-y lines and the z lines + product."""
     (K1, K2, K3), (n1, n2, n3) = K, n
     f = lambda m: 5.0 * m * math.log2(m)
-    lines = (K2 * K3 * f(n1) + n1 * K3 * f(n2) + n1 * n2 * f(n3)) * 2
-    return nrhs * ndir * (lines + 6.0 * n1 * n2 * n3)
+    xy = 2 * (K2 * K3 * f(n1) + n1 * K3 * f(n2))
+    z = 2 * n1 * n2 * f(n3) + 6.0 * n1 * n2 * n3
+    return nrhs * ndir * xy, nrhs * ndir * z
+
+
+def kernel_work(name, fmt, prec, ranks, info, K, n, ndir, nrhs):
+    """Algorithmic work of one launch of a library kernel: (MFMA flops, VALU flops,
+    HBM bytes).  Bytes count only what the method must move (the stored operator,
+    A read once, B written once); the half spectrum the three-pass pipeline keeps
+    between its passes is not algorithmic, nor are the z-major copies."""
+    a1, a2 = restore_macs(fmt, ranks, n, ndir)
+    xy, z = fft_flops(K, n, ndir, nrhs)
+    io = 8 * ndir * nrhs * K[0] * K[1] * K[2]
+    stored = info["bytes_stored"]
+    if name.startswith("fused"):
+        return 8.0 * a2, xy + z, stored + 2 * io
+    if name.startswith("zstage"):
+        return 8.0 * a2, z, stored
+    if name == "fwd_xy" or name == "inv_xy":
+        return 0.0, xy / 2, io
+    if name.startswith("a1_"):
+        return 8.0 * a1, 0.0, stored
+    return 0.0, 0.0, 0
+
+
+def roofline_of(name, avg_ms, work, prec):
+    """Most binding of HBM / MFMA / VALU for a kernel's algorithmic work over its
+    measured duration.  MFMA flops are the method's (8 per complex MAC), priced at
+    the peak of the arithmetic that runs them: FP32 MFMA, or bf16 MFMA for bf16x3
+    (which spends three bf16 products per FP32 product; that factor is reported
+    separately, not counted as work)."""
+    mf, vf, by = work
+    t = avg_ms * 1e-3
+    mpeak = PEAK_BF16_MFMA_TFLOPS if (prec == "bf16x3" and not name.startswith("a1_")) else PEAK_FP32_MFMA_TFLOPS
+    cand = [("hbm", by / t / 1e9, PEAK_HBM_GBS, "GB/s", by)]
+    if mf:
+        cand.append(("mfma", mf / t / 1e12, mpeak, "TFLOP/s", mf))
+    if vf:
+        cand.append(("alu", vf / t / 1e12, PEAK_FP32_VALU_TFLOPS, "TFLOP/s", vf))
+    b = max(cand, key=lambda c: c[1] / c[2])
+    out = {"bound": b[0], "achieved": round(b[1], 3), "peak": b[2], "unit": b[3], "frac": round(b[1] / b[2], 4),
+           "kernel": name, "kernel_avg_ms": avg_ms, "algorithmic": b[4],
+           "other_bound": {c[0]: {"achieved": round(c[1], 3), "peak": c[2], "unit": c[3],
+                                  "frac": round(c[1] / c[2], 4)} for c in cand if c[0] != b[0]}}
+    if prec == "bf16x3" and mf and not name.startswith("a1_"):
+        out["bf16_products_tflops"] = round(3 * mf / t / 1e12, 3)
+    return out
 
 
 def time_steps(ctx, op, A, B, steps, warmup, torch):
@@ -111,7 +167,7 @@ def time_steps(ctx, op, A, B, steps, warmup, torch):
         ctx.translate(op, A, B)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    nl = min(steps, 200)
+    nl = max(steps, 20)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
     for i in range(nl):
         evs[i][0].record(st)
@@ -121,7 +177,7 @@ def time_steps(ctx, op, A, B, steps, warmup, torch):
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     ctx.set_profiling(True)
     ctx.kernel_times(reset=True)
-    for _ in range(min(steps, 100)):
+    for _ in range(max(steps, 10)):
         ctx.translate(op, A, B)
     torch.cuda.synchronize()
     ctx.set_profiling(False)
@@ -129,58 +185,118 @@ def time_steps(ctx, op, A, B, steps, warmup, torch):
     return (t1 - t0) / steps * 1e3, lat, kt
 
 
-def cpu_baseline(w, fmt, gpu_Bs, A_np, target_s):
-    """The FP64 oracle on a bounded sample of directions: restoration + FFT convolution timed
-    on the host; also the reference each GPU result (one per precision) is checked against
-    on that sample: relative L2 error per direction, max and median."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+# --- CPU leg: the FP64 oracle, run in a child process --------------------------------
+_LEG = {}
+
+
+def _leg_direction(p):
     import oracle as O
 
+    comp, A = _LEG["comp"], _LEG["A"]
+    t0 = time.perf_counter()
+    Tp = O.restore_direction(comp, p)
+    O.translate_fft(A[:, p:p + 1], Tp[None])
+    return time.perf_counter() - t0
+
+
+def cpu_leg(args):
+    """Child process: the oracle as it stands (sampling, FFT and compression untimed),
+    then, once the parent's GPU work is done, (i) the error of the GPU results on a
+    direction sample against the exact FP64 translation and (ii) the oracle's
+    restoration + FFT convolution timed over directions on every host core."""
+    import multiprocessing as mp
+
+    import oracle as O
+
+    w = workload(args.workload)
+    fmt = args.fmt
+    khat, _ = O.directions(w.L, w.grid)
+    Th = O.fft_operator(O.sample_operator(w.K, w.box, w.k, w.L, khat))
+    comp = O.compress(Th, fmt, w.tol)
+    A = synth.patterns_for(w).astype(np.complex128)
+    print("ready", flush=True)
+    line = sys.stdin.readline().split()
+    if not line or line[0] != "go":
+        return
+    got = np.load(line[1])
+    sample = [int(p) for p in got["sample"]]
+    precs = [k for k in got.files if k != "sample"]
+    errs = {q: [] for q in precs}
+    errs_oracle = []
+    for i, p in enumerate(sample):
+        ex = O.translate_fft(A[:, p:p + 1], Th[p][None])
+        Bc = O.translate_fft(A[:, p:p + 1], O.restore_direction(comp, p)[None])
+        errs_oracle.append(O.rel_l2(Bc, ex))
+        for q in precs:
+            errs[q].append(max(O.rel_l2(got[q][s, i], ex[s, 0]) for s in range(A.shape[0])))
+    del Th
+    _LEG["comp"], _LEG["A"] = comp, A
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(cores, 64))
+    one = _leg_direction(0)  # warm, single direction, for sizing the sample
+    ndir = khat.shape[0]
+    # about cpu_seconds of CPU work: directions in a seeded order, cycled if the
+    # workload has fewer
+    nsamp = int(min(50 * ndir, max(cores, args.cpu_seconds / max(one, 1e-6))))
+    perm = np.random.default_rng(12345).permutation(ndir)
+    order = np.resize(perm, nsamp)
+    os.environ["OMP_NUM_THREADS"] = "1"
     try:
         from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(limits=1)
     except Exception:  # pragma: no cover
-        threadpool_limits = None
-    khat, _ = O.directions(w.L, w.grid)
-    ndir = khat.shape[0]
-    rng = np.random.default_rng(12345)
-    # grow the sample until it costs about target_s seconds
-    sample = []
-    t_total = 0.0
-    errs = {p: [] for p in gpu_Bs}
-    errs_exact = []
-    order = rng.permutation(ndir)
-    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
-        for p in order:
-            T = O.sample_operator(w.K, w.box, w.k, w.L, khat[p:p + 1])
-            Th = O.fft_operator(T)
-            comp = O.compress(Th, fmt, w.tol) if fmt != "full" else {"fmt": "full", "T": Th}
-            Ap = A_np[:, p:p + 1].astype(np.complex128)
-            t0 = time.perf_counter()
-            Bc = O.translate_compressed(Ap, comp)
-            t_total += time.perf_counter() - t0
-            Bex = O.translate_fft(Ap, Th)
-            for prec, gB in gpu_Bs.items():
-                errs[prec].append(O.rel_l2(gB[:, p:p + 1], Bex))
-            errs_exact.append(O.rel_l2(Bc, Bex))
-            sample.append(int(p))
-            if t_total >= target_s or len(sample) >= ndir:
-                break
-    finally:
-        if ctxm is not None:
-            ctxm.__exit__(None, None, None)
-    units = w.boxes * len(sample) * A_np.shape[0]
-    return {
-        "value": units / t_total,
-        "unit": "grid-pts*dirs/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"{len(sample)} of {ndir} directions x {A_np.shape[0]} RHS of the {w.name} workload "
-                  f"({fmt} restore + FFT convolution, FP64 numpy, 1 thread); {t_total:.1f} s",
-        "cpu": platform.processor() or platform.machine(),
-        "gpu_rel_err_max": {p: float(max(e)) for p, e in errs.items()},
-        "gpu_rel_err_median": {p: float(np.median(e)) for p, e in errs.items()},
-        "oracle_compressed_rel_err_max": float(max(errs_exact)),
-    }
+        lim = None
+    with mp.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        per = pool.map(_leg_direction, [int(p) for p in order], chunksize=1)
+        wall = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    units = w.boxes * nsamp * A.shape[0]
+    print(json.dumps({
+        "value": units / wall, "unit": "grid-pts*dirs/s", "cores": cores, "kind": "oracle",
+        "sample": f"{nsamp} direction tasks ({ndir} directions) x {A.shape[0]} RHS of the {w.name} workload ({fmt} "
+                  f"restoration + FFT convolution, FP64 numpy/scipy, one direction per task on {cores} "
+                  f"single-threaded worker processes); wall {wall:.2f} s, CPU work {sum(per):.1f} s",
+        "cpu_model": _cpu_model(), "cpu_seconds": sum(per), "wall_seconds": wall,
+        "gpu_rel_err_max": {q: float(max(e)) for q, e in errs.items()},
+        "gpu_rel_err_median": {q: float(np.median(e)) for q, e in errs.items()},
+        "error_sample_directions": sample,
+        "oracle_compressed_rel_err_max": float(max(errs_oracle)),
+    }), flush=True)
+
+
+def start_cpu_leg(args, fmt):
+    import subprocess
+
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-leg", "--workload", args.workload, "--fmt", fmt,
+           "--cpu-seconds", str(args.cpu_seconds)]
+    env = dict(os.environ, CUDA_VISIBLE_DEVICES="", HIP_VISIBLE_DEVICES="")
+    return subprocess.Popen(cmd, stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+
+
+def finish_cpu_leg(proc, npz_path):
+    line = proc.stdout.readline()
+    if line.strip() != "ready":
+        proc.kill()
+        raise RuntimeError("CPU leg failed during preparation")
+    proc.stdin.write(f"go {npz_path}\n")
+    proc.stdin.flush()
+    out = proc.stdout.readline()
+    proc.wait(timeout=600)
+    if proc.returncode != 0 or not out.strip():
+        raise RuntimeError("CPU leg failed")
+    return json.loads(out)
 
 
 SERVING_SKIP = {
@@ -191,12 +307,16 @@ SERVING_SKIP = {
 }
 
 
-SERVING_BUDGET_BYTES = 1536 << 20
+# HBM budget of the serving context: the compressed operators (~0.5 GB), the
+# A and B of the jobs in flight (up to 3.8 GB for a 16-RHS job on 32^3 boxes)
+# and translation scratch fit; the uncompressed operators of the same grids
+# (~2 GB) beside the largest jobs would not.
+SERVING_BUDGET_BYTES = 6 << 30
+SERVING_VERIFY = 24  # requests whose outputs are compared bit for bit with a solo translation
 
 
 def bench_serving(args):
     """Poisson stream of translation requests through tfmm_submit / tfmm_poll."""
-    import threading
 
     import torch
 
@@ -236,10 +356,24 @@ def bench_serving(args):
         for key, op in ops.items():
             g = key[0]
             ctx.wait(ctx.submit(op, inputs[g][:1], rings[g][0][:1]))
-        lock = threading.Lock()
         busy = {g: [0] * 8 for g in rings}
         pending, lat, units_done = [], [], [0]
+        failed = []
+        verify_ids = set(int(i) for i in np.random.default_rng(99).choice(len(reqs), SERVING_VERIFY, replace=False))
+        kept = {}  # request id -> copy of its served output
         waits, wait_s = 0, 0.0  # requests that found every output slot of their grid busy
+
+        def retire(item, st, l):
+            t, g, slot, units, rid, nr = item
+            if st != 0:
+                failed.append((rid, st))
+            else:
+                lat.append(l)
+                units_done[0] += units
+                if rid in verify_ids:
+                    kept[rid] = rings[g][slot][:nr].clone()
+            busy[g][slot] = 0
+
         t_start = time.perf_counter()
         for r in reqs:
             now = time.perf_counter() - t_start
@@ -252,9 +386,7 @@ def bench_serving(args):
                 for item in list(pending):
                     done, st, l = ctx.poll(item[0])
                     if done:
-                        lat.append(l)
-                        units_done[0] += item[3]
-                        busy[item[1]][item[2]] = 0
+                        retire(item, st, l)
                         pending.remove(item)
                 free = [i for i, b in enumerate(busy[g]) if not b]
                 if free:
@@ -268,12 +400,22 @@ def bench_serving(args):
             slot = free[0]
             busy[g][slot] = 1
             t = ctx.submit(ops[(g, r["fmt"])], inputs[g][:nr], rings[g][slot][:nr])
-            pending.append((t, g, slot, nr * ndir * g[0] * g[1] * g[2]))
+            pending.append((t, g, slot, nr * ndir * g[0] * g[1] * g[2], r["id"], nr))
         for item in pending:
             st, l = ctx.wait(item[0])
-            lat.append(l)
-            units_done[0] += item[3]
+            retire(item, st, l)
         wall = time.perf_counter() - t_start
+        stats = ctx.sched_stats()
+        # served outputs of a seeded sample of requests against a solo translation
+        mismatched = []
+        for r in reqs:
+            if r["id"] in kept:
+                g, nr = r["grid"], r["nrhs"]
+                solo = torch.empty_like(inputs[g][:nr])
+                ctx.translate(ops[(g, r["fmt"])], inputs[g][:nr], solo)
+                torch.cuda.synchronize()
+                if not torch.equal(solo, kept[r["id"]]):
+                    mismatched.append(r["id"])
         for op in ops.values():
             op.release()
     lat = np.array(lat) / 1e3  # ms
@@ -291,7 +433,10 @@ def bench_serving(args):
         "higher_is_better": True,
         "dtype": "f32",
         "data": "synthetic",
-        "admission_waits": {"requests": waits, "total_ms": wait_s * 1e3},
+        "failed_requests": len(failed),
+        "verified_bitwise_vs_solo": {"requests": len(kept), "mismatched": mismatched},
+        "scheduler": stats,
+        "client_output_slot_waits": {"requests": waits, "total_ms": wait_s * 1e3},
         "config": {"workload": "serving", "L": L, "n_dir": ndir, "tol": 1e-4, "hbm_budget_bytes": budget,
                    "operators_stored_bytes": bytes_stored, "uncompressed_operators_bytes": bytes_full,
                    "operators": [f"{g}-{f}" for g, f in keys],
@@ -300,6 +445,9 @@ def bench_serving(args):
         "memory_fraction": stored,
     }
     print(json.dumps(out))
+    if failed or mismatched:
+        sys.stderr.write(f"serving: {len(failed)} failed requests, {len(mismatched)} outputs differ from solo runs\n")
+        sys.exit(1)
 
 
 def bench_precision(args):
@@ -370,26 +518,116 @@ def bench_precision(args):
     }))
 
 
+def run_workload(ctx, w, fmt, precs, side, steps, warmup, torch, P, with_B=False, sample=None):
+    """Time the compressed operator (each precision, then each side format in the
+    first precision) and FULL on one workload, tile plans from tfmm_autotune."""
+    A_np = synth.patterns_for(w)
+    A = torch.from_numpy(A_np).cuda()
+    res = {}
+    exported = None
+    for prec in precs:
+        B = torch.zeros_like(A)
+        t0 = time.perf_counter()
+        if exported is None:
+            op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
+            exported = (list(op.ranks()), op.export())
+        else:
+            # the same factors in the other arithmetic (the compression does not
+            # depend on it)
+            op = ctx.import_factors(w.K, w.L, fmt, exported[0], exported[1], prec=prec)
+        setup_s = time.perf_counter() - t0
+        tuned = ctx.autotune(op, nrhs=w.nrhs, reps=5)
+        ms, lat, kt = time_steps(ctx, op, A, B, steps, warmup, torch)
+        r = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": list(op.ranks()), "setup_s": setup_s,
+             "plan": op.plan(), "autotune": tuned}
+        if with_B:
+            r["B_sample"] = B[:, sample].cpu().numpy()
+        res[(fmt, prec)] = r
+        op.release()
+    for xf in side:
+        t0 = time.perf_counter()
+        op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=xf, tol=w.tol, prec=precs[0])
+        setup_s = time.perf_counter() - t0
+        ctx.autotune(op, nrhs=w.nrhs, reps=5)
+        B = torch.zeros_like(A)
+        ms, lat, kt = time_steps(ctx, op, A, B, steps, warmup, torch)
+        res[(xf, precs[0])] = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": list(op.ranks()),
+                               "setup_s": setup_s, "plan": op.plan()}
+        op.release()
+    full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
+    ctx.autotune(full, nrhs=w.nrhs, reps=5)
+    Bf = torch.zeros_like(A)
+    ms_f, lat_f, kt_f = time_steps(ctx, full, A, Bf, steps, warmup, torch)
+    res[("full", "fp32")] = {"ms": ms_f, "lat": lat_f, "kt": kt_f, "info": full.info(), "ranks": [],
+                             "plan": full.plan()}
+    full.release()
+    del A
+    return res
+
+
+def summarize(w, key, r, full, steps):
+    """One timed operator of a workload: throughput, step time, ratio to FULL, the
+    dominant kernel's roofline and the whole step's algorithmic rates."""
+    fmt, prec = key
+    units = w.boxes * w.n_dir * w.nrhs
+    info, kt = r["info"], r["kt"]
+    kernels = {}
+    for name, k in kt.items():
+        per_step = k["launches"] / max(steps, 10)
+        work = kernel_work(name, fmt, prec, r["ranks"], info, w.K, w.n, w.n_dir, w.nrhs)
+        kernels[name] = {"avg_ms": k["avg_ms"], "launches_per_step": per_step,
+                         **({"roofline": roofline_of(name, k["avg_ms"], work, prec)} if any(work) else {})}
+    dom = max(kt, key=lambda n: kt[n]["avg_ms"] * kt[n]["launches"])
+    a1, a2 = restore_macs(fmt, r["ranks"], w.n, w.n_dir)
+    xy, z = fft_flops(w.K, w.n, w.n_dir, w.nrhs)
+    io = 16 * units
+    step = {"algorithmic_bytes": info["bytes_stored"] + io, "restore_flops": 8.0 * (a1 + a2),
+            "fft_flops": xy + z}
+    t = r["ms"] * 1e-3
+    step["hbm_gbs"] = step["algorithmic_bytes"] / t / 1e9
+    step["hbm_frac"] = step["hbm_gbs"] / PEAK_HBM_GBS
+    step["fft_tflops"] = step["fft_flops"] / t / 1e12
+    step["alu_frac"] = step["fft_tflops"] / PEAK_FP32_VALU_TFLOPS
+    step["restore_tflops"] = step["restore_flops"] / t / 1e12
+    out = {"fmt": fmt, "precision": prec, "value": units / t, "ms_per_step": r["ms"],
+           "p50_ms": float(np.percentile(r["lat"], 50)), "p99_ms": float(np.percentile(r["lat"], 99)),
+           "memory_fraction": info["bytes_stored"] / full["info"]["bytes_stored"],
+           "time_ratio_compressed_over_full": r["ms"] / full["ms"], "ranks_max": info["ranks"][:6],
+           "rel_err_fro_setup": info["rel_err_fro"], "plan": r["plan"], "dominant_kernel": dom,
+           "kernels": kernels, "whole_step": step}
+    if "setup_s" in r:
+        out["setup_s"] = r["setup_s"]
+    return out
+
+
 def main():
     args = parse()
+    if args.cpu_leg:
+        return cpu_leg(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "serving":
         return bench_serving(args)
-    if args.workload == "precision":
+    if args.workload == "precision" and not args.fmt and not args.prec:
         return bench_precision(args)
+    w = workload(args.workload)
+    fmt, side = HEADLINE[args.workload]
+    if args.fmt:
+        fmt, side = args.fmt, ()
+    if args.no_extra:
+        side = ()
+    # the headline is split-BF16 (bf16x3, FP32 accumulation); FP32 is timed beside it
+    precs = [args.prec] if args.prec else ["bf16x3", "fp32"]
+    # the CPU oracle prepares its operator in a child process while the GPU runs
+    leg = None if args.no_cpu else start_cpu_leg(args, fmt)
+    import tempfile
+
     import torch
 
     import paper_2010_00520_amd as P
 
-    w = workload(args.workload)
-    fmt = args.fmt or w.fmt
-    # the compressed path is timed in both restoration arithmetics; the headline
-    # is split-BF16 (bf16x3, FP32 accumulation), FP32 is reported beside it
-    precs = [args.prec] if args.prec else ["bf16x3", "fp32"]
-    A_np = synth.patterns_for(w)
     dev = torch.device("cuda:0")
     if args.calibrate_copy:
         n = args.calibrate_copy << 18  # MiB -> float32 count
@@ -399,132 +637,72 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    A = torch.from_numpy(A_np).to(dev)
-    res = {}
+    # direction sample the GPU results are checked on against the FP64 oracle
+    rng = np.random.default_rng(2024)
+    sample = sorted({0, w.n_dir - 1} | {int(p) for p in rng.choice(w.n_dir, size=10, replace=False)})
     with P.Context(0) as ctx:
-        for prec in precs:
-            B = torch.zeros_like(A)
-            t0 = time.perf_counter()
-            op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=fmt, tol=w.tol, prec=prec)
-            setup_s = time.perf_counter() - t0
-            tune = args.autotune or args.workload == "batching"
-            tuned = ctx.autotune(op, nrhs=w.nrhs, reps=10) if tune else None
-            ms, lat, kt = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
-            res[prec] = {"ms": ms, "lat": lat, "kt": kt, "info": op.info(), "ranks": op.ranks(), "setup_s": setup_s,
-                         "plan": op.plan(), "autotune": tuned, "B": B.cpu().numpy().astype(np.complex128)}
-            op.release()
-        # the batching grid is also run with Tucker-4D (per-call core contraction
-        # + register-chained restoration, the format with the smallest operator there)
-        extra = {}
-        for xf in (["tucker4d"] if args.workload == "batching" and not args.fmt else []):
-            t0 = time.perf_counter()
-            op = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt=xf, tol=w.tol, prec=precs[0])
-            setup_s = time.perf_counter() - t0
-            ctx.autotune(op, nrhs=w.nrhs, reps=10)
-            B = torch.zeros_like(A)
-            ms_x, lat_x, kt_x = time_steps(ctx, op, A, B, args.steps, args.warmup, torch)
-            extra[xf] = {"ms": ms_x, "kt": kt_x, "info": op.info(), "setup_s": setup_s, "plan": op.plan()}
-            op.release()
-        full = ctx.setup(K=w.K, box=w.box, k=w.k, L=w.L, fmt="full")
-        if args.autotune or args.workload == "batching":
-            ctx.autotune(full, nrhs=w.nrhs, reps=10)
-        Bf = torch.zeros_like(A)
-        ms_f, lat_f, kt_f = time_steps(ctx, full, A, Bf, args.steps, args.warmup, torch)
-        finfo = full.info()
-        full.release()
-
-    ndir, nrhs = w.n_dir, w.nrhs
-    units = w.boxes * ndir * nrhs
-    n = w.n
-    prof_steps = min(args.steps, 100)
-
-    def roofline(prec, r):
-        kt, info = r["kt"], r["info"]
-        # dominant kernel of the compressed path (largest total time)
-        zname = max(kt, key=lambda k: kt[k]["avg_ms"] * kt[k]["launches"])
-        zms = kt[zname]["avg_ms"] * kt[zname]["launches"] / prof_steps  # per step
-        flops = restore_flops(fmt, r["ranks"], n, ndir)
-        io = 2 * 8 * units  # A read + B written, complex64
-        # the fused kernel moves A and B as well; the three-pass z-stage only reads the operator
-        alg_bytes = info["bytes_stored"] + (io if zname.startswith("fused") else 0)
-        valu_flops = fft_flops(w.K, n, ndir, nrhs) if zname.startswith("fused") else 0.0
-        mfma_tfs = flops / (zms * 1e-3) / 1e12
-        if prec == "bf16x3":
-            # each FP32 product is three bf16 products (hi*hi + hi*lo + lo*hi) on the bf16 matrix cores
-            cand = [("mfma", 3 * mfma_tfs, PEAK_BF16_MFMA_TFLOPS, "TFLOP/s")]
-        else:
-            cand = [("mfma", mfma_tfs, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s")]
-        cand.append(("hbm", alg_bytes / (zms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"))
-        if valu_flops:
-            cand.append(("alu", valu_flops / (zms * 1e-3) / 1e12, PEAK_FP32_VALU_TFLOPS, "TFLOP/s"))
-        bound = max(cand, key=lambda c: c[1] / c[2])
-        traffic = None
-        tpath = os.path.join(ROOT, "profiles", "traffic.json")
-        if os.path.exists(tpath):
-            try:
-                tr = json.load(open(tpath))
-                key = f"{args.workload}:{fmt}:{prec}:{zname}"
-                if key in tr and tr[key].get("kernel_sha") == _kernel_sha():
-                    traffic = tr[key]["bytes_per_launch"]
-            except Exception:
-                traffic = None
-        return {"bound": bound[0], "achieved": round(bound[1], 3), "peak": bound[2], "unit": bound[3],
-                "frac": round(bound[1] / bound[2], 4), "traffic": traffic, "kernel": zname,
-                "kernel_avg_ms": zms, "algorithmic_flops": flops, "algorithmic_bytes": alg_bytes,
-                "fft_flops": valu_flops,
-                "other_bound": {c[0]: {"achieved": round(c[1], 3), "peak": c[2], "unit": c[3],
-                                       "frac": round(c[1] / c[2], 4)} for c in cand if c[0] != bound[0]}}
-
-    head = precs[0]
-    r = res[head]
-    ms = r["ms"]
+        res = run_workload(ctx, w, fmt, precs, side, args.steps, args.warmup, torch, P, with_B=leg is not None,
+                           sample=sample)
+        others = {}
+        if not args.no_extra:
+            for name in [n for n in ("plain", "precision") if n != args.workload]:
+                ow = workload(name)
+                of, _ = HEADLINE[name]
+                ores = run_workload(ctx, ow, of, ["bf16x3"], (), min(args.steps, 20), 3, torch, P)
+                others[ow.name] = summarize(ow, (of, "bf16x3"), ores[(of, "bf16x3")], ores[("full", "fp32")],
+                                            min(args.steps, 20))
+                others[ow.name]["full_ms_per_step"] = ores[("full", "fp32")]["ms"]
+    full = res[("full", "fp32")]
+    head = summarize(w, (fmt, precs[0]), res[(fmt, precs[0])], full, args.steps)
+    dom = head["dominant_kernel"]
+    roof = dict(head["kernels"][dom]["roofline"])
+    roof["traffic"] = None
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tpath):
+        try:
+            tr = json.load(open(tpath))
+            key = f"{args.workload}:{fmt}:{precs[0]}:{dom}"
+            if key in tr and tr[key].get("kernel_sha") == _kernel_sha():
+                roof["traffic"] = tr[key]["bytes_per_launch"]
+        except Exception:
+            roof["traffic"] = None
+    units = w.boxes * w.n_dir * w.nrhs
     out = {
-        "metric": "translated grid-pts*dirs/s, compressed operator (vs uncompressed), rel err <= 1e-4",
-        "value": units / (ms * 1e-3),
+        "metric": METRIC,
+        "value": head["value"],
         "unit": "grid-pts*dirs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if head == "fp32" else "bf16x3 (split-bf16 MFMA, f32 accumulate; FFTs f32)",
+        "dtype": "f32 FFTs, bf16x3 restoration" if precs[0] == "bf16x3" else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "K": list(w.K), "box": w.box, "L": w.L, "n_dir": ndir, "fmt": fmt,
-                   "tol": w.tol, "nrhs": nrhs, "precision": head},
-        "p50_ms": float(np.percentile(r["lat"], 50)),
-        "p99_ms": float(np.percentile(r["lat"], 99)),
-        "uncompressed": {"value": units / (ms_f * 1e-3), "ms_per_step": ms_f,
-                         "p50_ms": float(np.percentile(lat_f, 50)), "p99_ms": float(np.percentile(lat_f, 99)),
-                         "kernels": kt_f},
-        "time_ratio_compressed_over_full": ms / ms_f,
-        "memory_fraction": r["info"]["bytes_stored"] / finfo["bytes_stored"],
-        "op": {"ranks_max": r["info"]["ranks"], "rel_err_fro": r["info"]["rel_err_fro"], "setup_s": r["setup_s"],
-               "bytes_stored": r["info"]["bytes_stored"], "bytes_full": finfo["bytes_stored"], "plan": r["plan"],
-               "autotune": r["autotune"]},
-        "kernels": r["kt"],
-        "fft_flops_per_step": fft_flops(w.K, n, ndir, nrhs),
-        "roofline": roofline(head, r),
+        "config": {"workload": w.name, "K": list(w.K), "box": w.box, "L": w.L, "n_dir": w.n_dir, "fmt": fmt,
+                   "tol": w.tol, "nrhs": w.nrhs, "precision": precs[0], "units_per_step": units},
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "time_ratio_compressed_over_full": head["time_ratio_compressed_over_full"],
+        "memory_fraction": head["memory_fraction"],
+        "uncompressed": summarize(w, ("full", "fp32"), full, full, args.steps),
+        "headline": head,
+        "roofline": roof,
         "cpu_baseline": None,
     }
-    for prec in precs[1:]:
-        q = res[prec]
-        out[prec] = {"value": units / (q["ms"] * 1e-3), "ms_per_step": q["ms"],
-                     "p50_ms": float(np.percentile(q["lat"], 50)), "p99_ms": float(np.percentile(q["lat"], 99)),
-                     "time_ratio_compressed_over_full": q["ms"] / ms_f, "kernels": q["kt"],
-                     "roofline": roofline(prec, q)}
-    if extra:
-        out["other_formats"] = {
-            xf: {"precision": precs[0], "value": units / (x["ms"] * 1e-3), "ms_per_step": x["ms"],
-                 "time_ratio_compressed_over_full": x["ms"] / ms_f,
-                 "memory_fraction": x["info"]["bytes_stored"] / finfo["bytes_stored"],
-                 "ranks": x["info"]["ranks"], "rel_err_fro": x["info"]["rel_err_fro"], "setup_s": x["setup_s"],
-                 "plan": x["plan"], "kernels": x["kt"]}
-            for xf, x in extra.items()}
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, fmt, {p: res[p]["B"] for p in precs}, A_np, args.cpu_seconds)
-        out["rel_err_vs_fp64"] = out["cpu_baseline"]["gpu_rel_err_max"][head]
+    for key, r in res.items():
+        if key != (fmt, precs[0]) and key[0] != "full":
+            out.setdefault("beside", {})[f"{key[0]}-{key[1]}"] = summarize(w, key, r, full, args.steps)
+    if others:
+        out["other_workloads"] = others
+    if leg is not None:
+        with tempfile.TemporaryDirectory() as d:
+            path = os.path.join(d, "gpu_sample.npz")
+            np.savez(path, sample=np.array(sample), **{q: res[(fmt, q)]["B_sample"] for q in precs})
+            out["cpu_baseline"] = finish_cpu_leg(leg, path)
+        out["rel_err_vs_fp64"] = out["cpu_baseline"]["gpu_rel_err_max"][precs[0]]
+        out["within_tolerance"] = bool(out["rel_err_vs_fp64"] <= 10 * w.tol + 1e-6)
     print(json.dumps(out))
 
 

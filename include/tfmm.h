@@ -88,17 +88,28 @@ typedef enum { TFMM_NEAR_CHEB = 0, TFMM_NEAR_KAPPA = 1 } tfmm_near_rule;
 
 /* Direction grid (Section II-A, text after Eq. (4)): n_theta Gauss-Legendre
  * nodes in cos(theta), ascending, times n_phi uniform nodes phi_j = 2 pi j /
- * n_phi; direction index p = i_theta * n_phi + j_phi. */
+ * n_phi; direction index p = i_theta * n_phi + j_phi.  An explicit list of
+ * directions may replace the grid (the restoration does not depend on how the
+ * directions were chosen). */
 typedef struct {
   int32_t K[3];            /* box grid Kx, Ky, Kz; each one of 4, 8, 12, 16, 24, 32,
                               Kx also 64 or 128, with Kx * Ky <= 2048
                               (FFT grid n_i = 2 K_i)                                */
   double box_size;         /* box edge a, in the length unit of 1/k                  */
-  double k;                /* real wavenumber (lossless medium)                       */
+  double k_re, k_im;       /* wavenumber k = k_re + i k_im (Section II-A, Eq. (7));
+                              k_re > 0.  A lossy medium (Section III-A-5:
+                              k = k0 sqrt(eps_r) with eps_r = eps' - j sigma/(w eps0))
+                              has k_im < 0 under the e^{jwt} convention, so that
+                              e^{-jkR} decays; k_im > 0 is rejected                 */
   int32_t L;               /* multipole order; 0 => derive it from `digits`         */
   double digits;           /* accurate digits, used only when L == 0:
-                              L = ceil(x + 1.8 digits^(2/3) x^(1/3)), x = k a sqrt(3) */
+                              L = ceil(x + 1.8 digits^(2/3) x^(1/3)), x = |k| a sqrt(3) */
   int32_t n_theta, n_phi;  /* 0,0 => L+1 and 2(L+1)                                   */
+  const double* dirs;      /* optional: n_dir x 3 unit vectors k_p (host memory, read
+                              during the call only); when set it replaces the
+                              n_theta x n_phi grid and direction p is dirs[3p..3p+2] */
+  int32_t n_dir;           /* number of rows of `dirs`; for tfmm_op_import, which
+                              samples nothing, a direction count without `dirs`    */
   tfmm_near_rule near_rule;
   double near_param;       /* 0 => 1 for CHEB, 4 for KAPPA                            */
   double scale_re, scale_im; /* global prefactor of Eq. (7); 0,0 => 1                 */
@@ -117,6 +128,12 @@ typedef struct {
   size_t bytes_full;       /* complex64 bytes of the uncompressed operator           */
   size_t bytes_stored;     /* device bytes of the stored operator                    */
   size_t elems_stored;     /* complex entries of cores and factors                   */
+  size_t bytes_scratch;    /* device bytes of translation scratch a one-RHS
+                              tfmm_translate of this operator takes from the
+                              context (half spectrum of one chunk of directions,
+                              per-direction cores of the 4-D formats, z-major
+                              copies); it grows with the RHS count up to the
+                              context's chunk size                                  */
   double rel_err_fro;      /* ||T~ - T~hat||_F / ||T~||_F over all directions, FP64 at setup */
   double max_dir_rel_err;  /* max over directions of the same ratio                  */
   int32_t ranks[8];        /* format ranks; 3-D formats: maximum over directions     */
@@ -215,11 +232,20 @@ tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int
 
 /* ---- serving: continuous batching (submit / poll) ------------------------ */
 
-/* Queue a translation job for the context's scheduler thread.  A and B as for
- * tfmm_translate and caller-owned until the job is reported done.  The job
- * keeps a reference on `op`.  Jobs that arrive while others run are admitted
- * as scratch memory frees up and are batched with other jobs on the same
- * operator.  Returns at once with a ticket. */
+/* Queue a translation job for the context's scheduler thread (continuous
+ * batching of the translation of Eq. (5)).  A and B as for tfmm_translate and
+ * caller-owned until the job is reported done; A must be complete on the
+ * device when the job is submitted (the scheduler's streams do not wait for
+ * the caller's streams).  The job keeps a reference on `op`.
+ * Admission, in arrival order: a job is started on one of two scheduler
+ * streams once a stream is free and its memory fits the context's budget --
+ * its A and B bytes (2 x nrhs x n_dir x Kx x Ky x Kz complex64) plus the
+ * stream's translation scratch (whose direction chunk shrinks, down to one
+ * direction, to fit).  A job that does not fit waits at the head of the queue
+ * until a running job completes and returns its memory; it fails with
+ * TFMM_ERR_BUDGET only if it cannot fit with no other job running.  Queued
+ * jobs on the same operator are started together in one batched launch.
+ * Returns at once with a ticket. */
 tfmm_status tfmm_submit(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
                         tfmm_ticket* out);
 
@@ -230,6 +256,11 @@ tfmm_status tfmm_poll(tfmm_ctx ctx, tfmm_ticket t, int32_t* done, tfmm_status* j
 
 /* Block until the job is done; the ticket is then retired. */
 tfmm_status tfmm_wait(tfmm_ctx ctx, tfmm_ticket t, tfmm_status* job_status, double* latency_us);
+
+/* Scheduler counters since the context was created: {launches started, times
+ * the head of the queue waited for memory, jobs completed, jobs failed, jobs
+ * queued now}; writes min(cap, 5) values. */
+tfmm_status tfmm_sched_stats(tfmm_ctx ctx, uint64_t* out, size_t cap);
 
 /* ---- batching: tile autotuner ------------------------------------------------ */
 

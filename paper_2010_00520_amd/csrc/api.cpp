@@ -92,6 +92,8 @@ struct tfmm_op_s {
   bool tk2 = false, ftk2 = false;
   size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
   int* d_perm = nullptr;               // direction order, costliest restoration first (NULL: identity)
+  float2* d_roots_z = nullptr;         // exp(-2 pi i m / n3), m < n3 (context table)
+  float2* d_roots_x = nullptr;         // exp(-2 pi i m / n1) when n1 > 64 (context table), else NULL
   // captured translations, keyed by (nrhs, A, B) and the scratch generation
   struct GraphEntry {
     int nrhs;
@@ -115,6 +117,7 @@ struct Job {
   float2* B = nullptr;
   int nrhs = 0;
   double t_submit = 0.0, t_done = 0.0;
+  size_t charged = 0;                  // A and B bytes charged to the budget while admitted
   std::atomic<int> done{0};
   tfmm_status status = TFMM_OK;
 };
@@ -141,6 +144,10 @@ struct tfmm_ctx_s {
   static constexpr int kSlots = 3;
   ScratchSlot scratch[kSlots];
   unsigned scratch_gen[kSlots] = {0, 0, 0};  // bumped when a slot's buffer moves
+  // recorded after the last work enqueued on each slot's scratch: a slot's buffer
+  // is freed only once its own work is done (no device-wide synchronisation)
+  hipEvent_t slot_ev[kSlots] = {nullptr, nullptr, nullptr};
+  bool slot_ev_set[kSlots] = {false, false, false};
   int* counters = nullptr;             // device work counters of the persistent launches, one per slot
   int ncu = 0;                         // compute units
   hipStream_t cap_stream = nullptr;    // stream used only for graph capture
@@ -181,6 +188,9 @@ struct tfmm_ctx_s {
   std::atomic<tfmm_ticket> next_ticket{1};
   bool stop = false;
   int slot_busy[2] = {0, 0};
+  // scheduler statistics: launches started, times the head of the queue had to
+  // wait for memory, jobs completed and jobs failed
+  uint64_t n_launch = 0, n_parked = 0, n_done = 0, n_failed = 0;
   std::vector<tfmm_op> ops;
 };
 
@@ -217,15 +227,25 @@ void dev_free(tfmm_ctx c, void* p, size_t bytes) {
   }
 }
 
+void mark_slot(tfmm_ctx c, int slot, hipStream_t st) {
+  if (hipEventRecord(c->slot_ev[slot], st) == hipSuccess) c->slot_ev_set[slot] = true;
+}
+
+// Free a slot's scratch once the work enqueued on it has finished.
+void release_scratch(tfmm_ctx c, int slot) {
+  ScratchSlot& s = c->scratch[slot];
+  if (!s.ptr) return;
+  if (c->slot_ev_set[slot]) (void)hipEventSynchronize(c->slot_ev[slot]);
+  dev_free(c, s.ptr, s.bytes);
+  s.ptr = nullptr;
+  s.bytes = 0;
+  ++c->scratch_gen[slot];
+}
+
 tfmm_status ensure_scratch(tfmm_ctx c, int slot, size_t bytes, void** out) {
   ScratchSlot& s = c->scratch[slot];
   if (s.bytes < bytes) {
-    if (s.ptr) {
-      (void)hipDeviceSynchronize();
-      dev_free(c, s.ptr, s.bytes);
-      s.ptr = nullptr;
-      s.bytes = 0;
-    }
+    release_scratch(c, slot);
     size_t want = bytes + bytes / 8;
     tfmm_status st = dev_alloc(c, &s.ptr, want);
     if (st != TFMM_OK) {
@@ -374,6 +394,10 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nd = op->ndir;
   const long long N = (long long)n1 * n2 * n3;
   op->nq = n1 * n2;
+  // twiddle tables of the z-stage and of long x lines, shared per context
+  tfmm_status st0 = roots_table(c, n3, &op->d_roots_z);
+  if (st0 == TFMM_OK && n1 > 64) st0 = roots_table(c, n1, &op->d_roots_x);
+  if (st0 != TFMM_OK) return st0;
   if (op->fmt == TFMM_FMT_FULL) {
     std::vector<float4> h((size_t)nd * N / 2);
     for (int p = 0; p < nd; ++p)
@@ -474,6 +498,36 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
   return plan_zstage(op);
 }
 
+// Scratch of one translation: the half spectrum of a chunk of ndl directions
+// (three-pass pipeline), the per-direction cores of the 4-D formats, and the
+// z-major copies of A and B for short z extents.
+struct ScratchPlan {
+  int ndl = 1;
+  int rhs_group = 1;
+  bool zm = false;
+  size_t hbytes = 0, a1b = 0, zbytes = 0;
+  size_t total() const { return hbytes + a1b + zbytes; }
+};
+
+ScratchPlan scratch_plan(const tfmm_op_s* op, int nr_total, size_t cap) {
+  ScratchPlan sp;
+  const int K3 = op->K[2], nd = op->ndir;
+  const size_t per_dir_rhs = (size_t)K3 * op->nq * sizeof(float2);
+  sp.rhs_group = std::max(1, std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH));
+  sp.ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, cap / (per_dir_rhs * sp.rhs_group)));
+  sp.hbytes = op->fused ? 0 : per_dir_rhs * sp.rhs_group * sp.ndl;
+  // three-pass: A and B go through z-major copies (a z-slab of a box block is
+  // then contiguous for the xy passes; in the caller's layout it is strided by
+  // K3).  Measured faster for K3 = 8 and 16 (e.g. 256x16x16: xy passes 258 ->
+  // 227 us per launch with the copies), slower for K3 = 24 and 32.
+  sp.zm = !op->fused && K3 >= 8 && K3 <= 16;
+  const long long box = (long long)op->K[0] * op->K[1] * K3;
+  sp.zbytes = sp.zm ? (size_t)box * sp.rhs_group * sp.ndl * sizeof(float2) : 0;
+  sp.hbytes = (sp.hbytes + 255) / 256 * 256;
+  sp.a1b = (op->a1_bytes + 255) / 256 * 256;
+  return sp;
+}
+
 void fill_info(tfmm_op op, double setup_s) {
   tfmm_op_info& I = op->info;
   I = tfmm_op_info();
@@ -488,6 +542,7 @@ void fill_info(tfmm_op op, double setup_s) {
   I.bytes_full = (size_t)op->ndir * op->n[0] * op->n[1] * op->n[2] * 8;
   I.bytes_stored = op->stored_elems * 8;
   I.elems_stored = op->stored_elems;
+  I.bytes_scratch = scratch_plan(op, 1, op->ctx->hcap).total();
   I.rel_err_fro = op->host.rel_err;
   I.max_dir_rel_err = op->host.max_dir_err;
   for (int i = 0; i < 8; ++i) I.ranks[i] = 0;
@@ -510,11 +565,27 @@ tfmm_status check_problem(const tfmm_problem* P, int* ndir, int* L, int* nth, in
   if ((int)P->prec < 0 || (int)P->prec > 1) return fail(TFMM_ERR_INVALID_ARG, "unknown precision");
   int l = P->L;
   if (l <= 0) {
-    if (!(P->digits > 0) || !(P->k > 0) || !(P->box_size > 0))
+    const double kabs = std::hypot(P->k_re, P->k_im);
+    if (!(P->digits > 0) || !(kabs > 0) || !(P->box_size > 0))
       return fail(TFMM_ERR_INVALID_ARG, "L == 0 needs positive digits, k and box_size");
-    l = tfmm::multipole_order_ceil(P->k, P->box_size, P->digits);
+    l = tfmm::multipole_order_ceil(kabs, P->box_size, P->digits);
   }
   if (l > 200) return fail(TFMM_ERR_INVALID_ARG, "multipole order too large");
+  if (P->dirs) {
+    // explicit direction list: unit vectors, the grid fields must be unset
+    if (P->n_dir < 1 || P->n_dir > 100000) return fail(TFMM_ERR_INVALID_ARG, "n_dir out of range for dirs");
+    if (P->n_theta > 0 || P->n_phi > 0) return fail(TFMM_ERR_INVALID_ARG, "dirs and n_theta/n_phi are exclusive");
+    for (int p = 0; p < P->n_dir; ++p) {
+      const double* d = P->dirs + 3 * (size_t)p;
+      const double nn = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (!(std::fabs(nn - 1.0) <= 1e-9)) return fail(TFMM_ERR_INVALID_ARG, "dirs must hold unit vectors");
+    }
+    *L = l;
+    *nth = 0;
+    *nph = 0;
+    *ndir = P->n_dir;
+    return TFMM_OK;
+  }
   int a = P->n_theta > 0 ? P->n_theta : l + 1;
   int b = P->n_phi > 0 ? P->n_phi : 2 * (l + 1);
   if ((P->n_theta > 0) != (P->n_phi > 0)) return fail(TFMM_ERR_INVALID_ARG, "set both n_theta and n_phi or neither");
@@ -624,42 +695,33 @@ tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
   return TFMM_OK;
 }
 
-// Translate `nr` right-hand sides given by pointer tables, using scratch slot `slot`.
-tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2*>& As,
-                          const std::vector<float2*>& Bs, hipStream_t st, int slot) {
+// Enqueue the translation of `nr` right-hand sides (pointer tables) on `st`
+// with the scratch `scr` laid out by `sp`; `counter` = two ints of the
+// persistent launches, zero on entry and left zero.
+tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2*>& As,
+                              const std::vector<float2*>& Bs, hipStream_t st, void* scr, const ScratchPlan& sp,
+                              int* counter, bool prof) {
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], K3 = op->K[2], nd = op->ndir;
-  const size_t per_dir_rhs = (size_t)K3 * op->nq * sizeof(float2);
   const int nr_total = (int)As.size();
-  const size_t hcap = c->hcap;  // half-spectrum scratch per chunk
-  const int rhs_group = std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH);
-  int ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, hcap / (per_dir_rhs * rhs_group)));
-  const size_t hbytes = op->fused ? 0 : per_dir_rhs * rhs_group * ndl;
-  // three-pass: A and B go through z-major copies (a z-slab of a box block is
-  // then contiguous for the xy passes; in the caller's layout it is strided by
-  // K3).  Measured faster for K3 = 8 and 16 (e.g. 256x16x16: xy passes 258 ->
-  // 227 us per launch with the copies), slower for K3 = 24 and 32.
+  const int rhs_group = sp.rhs_group, ndl = sp.ndl;
+  const bool zm = sp.zm;
   const long long box = (long long)op->K[0] * op->K[1] * K3;
-  const bool zm = !op->fused && K3 >= 8 && K3 <= 16;
-  const size_t zbytes = zm ? (size_t)box * rhs_group * ndl * sizeof(float2) : 0;
-  const size_t a1b = (op->a1_bytes + 255) / 256 * 256;
-  void* scr = nullptr;
-  tfmm_status s = ensure_scratch(c, slot, hbytes + a1b + zbytes, &scr);
-  if (s != TFMM_OK) return s;
   float2* H = (float2*)scr;
-  float2* a1 = (float2*)((char*)scr + hbytes);
-  float2* Zs = (float2*)((char*)scr + hbytes + a1b);
+  float2* a1 = (float2*)((char*)scr + sp.hbytes);
+  float2* Zs = (float2*)((char*)scr + sp.hbytes + sp.a1b);
+  const bool prof0 = c->prof;
+  c->prof = prof0 && prof;
+  struct Restore {
+    tfmm_ctx c;
+    bool v;
+    ~Restore() { c->prof = v; }
+  } restore{c, prof0};
   if (op->a1_bytes) {
-    s = run_a1(c, op, a1, st);
+    tfmm_status s = run_a1(c, op, a1, st);
     if (s != TFMM_OK) return s;
   }
-  float2* roots = nullptr;
-  s = roots_table(c, n3, &roots);
-  if (s != TFMM_OK) return s;
-  float2* twx = nullptr;
-  if (n1 > 64) {
-    s = roots_table(c, n1, &twx);
-    if (s != TFMM_OK) return s;
-  }
+  float2* roots = op->d_roots_z;
+  float2* twx = op->d_roots_x;
   tfmm::ZArgs z{};
   z.fmt = op->zfmt;
   z.n1 = n1; z.n2 = n2; z.n3 = n3; z.K3 = K3; z.nq = op->nq;
@@ -678,7 +740,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   z.bf = op->prec == TFMM_PREC_BF16X3 ? 1 : 0;
   z.tk2 = op->tk2 ? 1 : 0;
   z.perm = op->d_perm;
-  z.counter = c->counters + 2 * slot;
+  z.counter = counter;
   z.ncu = c->ncu;
   const float scale = 1.0f / (float)((double)n1 * n2 * n3);
   if (op->fused) {
@@ -759,6 +821,25 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
   return TFMM_OK;
 }
 
+// Translate `nr` right-hand sides given by pointer tables, using scratch slot
+// `slot`.  The direction chunk starts at the context's chunk size and is
+// halved (down to one direction) while the scratch does not fit the budget.
+tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2*>& As,
+                          const std::vector<float2*>& Bs, hipStream_t st, int slot) {
+  size_t cap = c->hcap;
+  ScratchPlan sp = scratch_plan(op, (int)As.size(), cap);
+  void* scr = nullptr;
+  for (;;) {
+    tfmm_status s = ensure_scratch(c, slot, sp.total(), &scr);
+    if (s == TFMM_OK) break;
+    if (s != TFMM_ERR_BUDGET || sp.ndl <= 1) return s;
+    const int want = sp.ndl / 2;
+    while (scratch_plan(op, (int)As.size(), cap).ndl > want && cap > 1) cap /= 2;
+    sp = scratch_plan(op, (int)As.size(), cap);
+  }
+  return enqueue_translate(c, op, As, Bs, st, scr, sp, c->counters + 2 * slot, true);
+}
+
 // ---------------------------------------------------------------------------
 // Autotuner: tile configurations keyed by grid class, rank bucket, precision
 // and RHS bucket.
@@ -796,6 +877,7 @@ tfmm_status apply_choice(tfmm_op op, const TuneChoice& ch) {
     return s;
   }
   drop_graphs(op);
+  op->info.bytes_scratch = scratch_plan(op, 1, op->ctx->hcap).total();
   return TFMM_OK;
 }
 
@@ -830,10 +912,28 @@ tfmm_status translate_contiguous(tfmm_ctx c, tfmm_op op, const void* A, void* B,
 }
 
 // ---------------------------------------------------------------------------
-// Scheduler: a worker thread admits queued jobs, coalesces the ones on the same
-// operator into one batched launch per stream slot, and a completer thread
-// stamps completion when the slot's event fires.
+// Scheduler: a worker thread admits queued jobs in arrival order against the
+// device-memory budget, coalesces the ones on the same operator into one
+// batched launch per stream slot, and a completer thread stamps completion
+// when the slot's event fires and returns the jobs' memory to the budget.
+//
+// Admission charges each job's A and B (caller buffers, but device memory the
+// job occupies) and the slot's translation scratch.  A job that does not fit is
+// parked at the head of the queue until a running job completes; only a job
+// that cannot fit even with nothing else running fails (TFMM_ERR_BUDGET).
 // ---------------------------------------------------------------------------
+
+size_t job_io_bytes(const Job& j) {
+  return (size_t)2 * j.nrhs * j.op->ndir * j.op->K[0] * j.op->K[1] * j.op->K[2] * sizeof(float2);
+}
+
+// Bytes a batch needs beyond what is charged now: its A and B plus the growth of
+// the slot's scratch for the smallest direction chunk.
+size_t admission_need(tfmm_ctx c, tfmm_op op, int nr, size_t io, int slot) {
+  const size_t scr = scratch_plan(op, nr, 1).total();
+  const size_t have = c->scratch[1 + slot].bytes;
+  return io + (scr > have ? scr : 0);
+}
 
 void worker_loop(tfmm_ctx c) {
   (void)hipSetDevice(c->device);
@@ -847,7 +947,8 @@ void worker_loop(tfmm_ctx c) {
       });
       if (c->stop && c->queue.empty()) return;
       slot = c->slot_busy[0] == 0 ? 0 : 1;
-      // coalesce every queued job on the operator of the oldest job (up to 4 x the launch RHS cap)
+      // coalesce queued jobs on the operator of the oldest job (up to 4 x the
+      // launch RHS cap), in arrival order
       tfmm_op op = c->queue.front()->op;
       int nr = 0;
       for (auto it = c->queue.begin(); it != c->queue.end();) {
@@ -862,6 +963,70 @@ void worker_loop(tfmm_ctx c) {
       c->slot_busy[slot] = 1;
     }
     tfmm_op op = batch.front()->op;
+    // admission against the budget (the budget is guarded by c->mu)
+    bool park = false;
+    tfmm_status adm = TFMM_OK;
+    {
+      std::lock_guard<std::recursive_mutex> g(c->mu);
+      auto need_of = [&](size_t njobs) {
+        int nr = 0;
+        size_t io = 0;
+        for (size_t i = 0; i < njobs; ++i) {
+          nr += batch[i]->nrhs;
+          io += job_io_bytes(*batch[i]);
+        }
+        return admission_need(c, op, nr, io, slot);
+      };
+      size_t keep = batch.size();
+      while (keep > 1 && c->used + need_of(keep) > c->budget) --keep;
+      if (c->used + need_of(keep) > c->budget) {
+        // the oldest job alone does not fit: free the idle slot's scratch and retry
+        const int other = 1 - slot;
+        bool other_idle;
+        {
+          std::lock_guard<std::mutex> lk(c->qmu);
+          other_idle = c->slot_busy[other] == 0;
+        }
+        if (other_idle) release_scratch(c, 1 + other);
+        if (c->used + need_of(keep) > c->budget) {
+          release_scratch(c, 1 + slot);
+          if (other_idle && c->used + need_of(keep) > c->budget) release_scratch(c, 0);
+          if (c->used + need_of(keep) > c->budget) {
+            if (other_idle) {
+              // nothing else holds translation memory: the job can never fit
+              adm = fail(TFMM_ERR_BUDGET, "job needs " + std::to_string(need_of(keep)) + " B, " +
+                                              std::to_string(c->budget - std::min(c->budget, c->used)) +
+                                              " B of the budget are not held by operators");
+            } else {
+              park = true;
+            }
+          }
+        }
+      }
+      if (!park && adm == TFMM_OK) {
+        // jobs beyond `keep` go back to the head of the queue, in order
+        std::vector<std::shared_ptr<Job>> back(batch.begin() + keep, batch.end());
+        batch.resize(keep);
+        if (!back.empty()) {
+          std::lock_guard<std::mutex> lk(c->qmu);
+          c->queue.insert(c->queue.begin(), back.begin(), back.end());
+        }
+        for (auto& j : batch) {
+          j->charged = job_io_bytes(*j);
+          c->used += j->charged;
+        }
+      }
+    }
+    if (park) {
+      // back to the head of the queue; wait for a running job to complete
+      std::unique_lock<std::mutex> lk(c->qmu);
+      c->queue.insert(c->queue.begin(), batch.begin(), batch.end());
+      c->n_parked += 1;
+      c->slot_busy[slot] = 0;
+      const int other = 1 - slot;
+      c->fcv.wait(lk, [&] { return c->stop || c->slot_busy[other] == 0; });
+      continue;
+    }
     std::vector<const float2*> As;
     std::vector<float2*> Bs;
     const size_t blk = (size_t)op->ndir * op->K[0] * op->K[1] * op->K[2];
@@ -870,11 +1035,12 @@ void worker_loop(tfmm_ctx c) {
         As.push_back(j->A + s * blk);
         Bs.push_back(j->B + s * blk);
       }
-    tfmm_status st;
+    tfmm_status st = adm;
     hipEvent_t ev = nullptr;
-    {
+    if (st == TFMM_OK) {
       std::lock_guard<std::recursive_mutex> g(c->mu);
       st = run_translate(c, op, As, Bs, c->streams[slot], 1 + slot);
+      if (st == TFMM_OK) mark_slot(c, 1 + slot, c->streams[slot]);
       if (st == TFMM_OK && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess)
         (void)hipEventRecord(ev, c->streams[slot]);
     }
@@ -882,6 +1048,10 @@ void worker_loop(tfmm_ctx c) {
     f.ev = ev;
     f.jobs = batch;
     f.slot = slot;
+    if (st == TFMM_OK) {
+      std::lock_guard<std::mutex> lk(c->qmu);
+      c->n_launch += 1;
+    }
     if (st != TFMM_OK || !ev) {
       for (auto& j : batch) j->status = st != TFMM_OK ? st : TFMM_ERR_HIP;
       f.ev = nullptr;
@@ -912,9 +1082,20 @@ void completer_loop(tfmm_ctx c) {
     }
     const double t = now_s();
     {
+      std::lock_guard<std::recursive_mutex> g(c->mu);
+      for (auto& j : f.jobs) {
+        uncharge(c, j->charged);
+        j->charged = 0;
+      }
+    }
+    {
       std::lock_guard<std::mutex> lk(c->qmu);
       for (auto& j : f.jobs) {
         if (j->status == TFMM_OK) j->status = st;
+        if (j->status == TFMM_OK)
+          c->n_done += 1;
+        else
+          c->n_failed += 1;
         j->t_done = t;
         j->op->refs.fetch_sub(1);
         j->done.store(1);
@@ -1001,6 +1182,11 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
       delete c;
       return fail(TFMM_ERR_HIP, "stream creation failed");
     }
+  for (auto& e : c->slot_ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      delete c;
+      return fail(TFMM_ERR_HIP, "event creation failed");
+    }
   c->worker = std::thread(worker_loop, c);
   c->completer = std::thread(completer_loop, c);
   *out = c;
@@ -1030,6 +1216,7 @@ tfmm_status tfmm_ctx_destroy(tfmm_ctx c) {
   for (auto& s : c->scratch)
     if (s.ptr) (void)hipFree(s.ptr);
   for (auto& s : c->streams) (void)hipStreamDestroy(s);
+  for (auto& e : c->slot_ev) (void)hipEventDestroy(e);
   (void)hipStreamDestroy(c->cap_stream);
   (void)hipFree(c->counters);
   delete c;
@@ -1049,13 +1236,17 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* ou
   int ndir, L, nth, nph;
   tfmm_status s = check_problem(P, &ndir, &L, &nth, &nph);
   if (s != TFMM_OK) return s;
-  if (!(P->k > 0) || !(P->box_size > 0)) return fail(TFMM_ERR_INVALID_ARG, "k and box_size must be positive");
+  if (!(P->k_re > 0) || !(P->box_size > 0)) return fail(TFMM_ERR_INVALID_ARG, "k_re and box_size must be positive");
+  if (!(P->k_im <= 0)) return fail(TFMM_ERR_INVALID_ARG, "k_im must be <= 0 (a passive medium)");
   if (P->fmt != TFMM_FMT_FULL && !(P->tol >= 0 && P->tol < 1)) return fail(TFMM_ERR_INVALID_ARG, "tol must be in [0, 1)");
   const double t0 = now_s();
   std::lock_guard<std::recursive_mutex> g(c->mu);
   HIP_TRY(hipSetDevice(c->device));
   std::vector<double> khat, w;
-  tfmm::direction_grid(nth, nph, khat, w);
+  if (P->dirs)
+    khat.assign(P->dirs, P->dirs + 3 * (size_t)ndir);
+  else
+    tfmm::direction_grid(nth, nph, khat, w);
   const int n[3] = {2 * P->K[0], 2 * P->K[1], 2 * P->K[2]};
   const long long N = (long long)n[0] * n[1] * n[2];
   const size_t tbytes = (size_t)N * ndir * sizeof(double2);
@@ -1074,7 +1265,7 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* ou
   const double near_param = P->near_param > 0 ? P->near_param : (near_rule == 0 ? 1.0 : 4.0);
   const bool scale0 = P->scale_re == 0 && P->scale_im == 0;
   if (e == hipSuccess)
-    e = tfmm::launch_sample(d_T, d_khat, ndir, P->K, P->box_size, P->k, L, near_rule, near_param,
+    e = tfmm::launch_sample(d_T, d_khat, ndir, P->K, P->box_size, P->k_re, P->k_im, L, near_rule, near_param,
                             scale0 ? 1.0 : P->scale_re, scale0 ? 0.0 : P->scale_im, 0);
   if (e == hipSuccess) e = hipMemcpy(T.data(), d_T, tbytes, hipMemcpyDeviceToHost);
   (void)hipFree(d_T);
@@ -1108,9 +1299,21 @@ tfmm_status tfmm_op_import(tfmm_ctx c, const tfmm_problem* P, const int32_t* ran
   if (!c || !out) return fail(TFMM_ERR_INVALID_ARG, "ctx or out is NULL");
   int ndir, L, nth, nph;
   tfmm_problem Q = *P;
-  if (Q.L <= 0 && Q.n_theta <= 0) return fail(TFMM_ERR_INVALID_ARG, "import needs L or an explicit direction grid");
+  if (Q.L <= 0 && Q.n_theta <= 0 && Q.n_dir <= 0)
+    return fail(TFMM_ERR_INVALID_ARG, "import needs L, an explicit direction grid or a direction count");
+  int count_only = 0;
+  if (!Q.dirs && Q.n_dir > 0) {
+    // a direction count alone: nothing is sampled, so no directions are needed
+    if (Q.n_theta > 0 || Q.n_phi > 0) return fail(TFMM_ERR_INVALID_ARG, "n_dir and n_theta/n_phi are exclusive");
+    if (Q.n_dir > 100000) return fail(TFMM_ERR_INVALID_ARG, "n_dir out of range");
+    count_only = Q.n_dir;
+    Q.n_theta = 1;
+    Q.n_phi = Q.n_dir;
+    if (Q.L <= 0) Q.L = 1;
+  }
   tfmm_status s = check_problem(&Q, &ndir, &L, &nth, &nph);
   if (s != TFMM_OK) return s;
+  if (count_only) L = P->L > 0 ? P->L : 0;
   if (nranks && !ranks) return fail(TFMM_ERR_INVALID_ARG, "ranks is NULL");
   if (!data) return fail(TFMM_ERR_INVALID_ARG, "data is NULL");
   const int n[3] = {2 * P->K[0], 2 * P->K[1], 2 * P->K[2]};
@@ -1205,8 +1408,11 @@ tfmm_status tfmm_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32
   // multi-launch sequences (three-pass pipeline, per-call core contraction)
   // are captured once per (nrhs, A, B) and replayed.
   const bool multi = !op->fused || op->a1_bytes > 0;
-  if (c->prof || c->graph_mode == 0 || (c->graph_mode == 2 && !multi))
-    return translate_contiguous(c, op, A, B, nrhs, st, 0);
+  if (c->prof || c->graph_mode == 0 || (c->graph_mode == 2 && !multi)) {
+    s = translate_contiguous(c, op, A, B, nrhs, st, 0);
+    if (s == TFMM_OK) mark_slot(c, 0, st);
+    return s;
+  }
   // replay a captured translation of the same (nrhs, A, B) if its scratch is still in place
   auto& G = op->graphs;
   for (size_t i = 0; i < G.size(); ++i) {
@@ -1216,6 +1422,7 @@ tfmm_status tfmm_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32
     if (e.gen == c->scratch_gen[0]) {
       G.push_back(e);
       HIP_TRY(hipGraphLaunch(e.x, st));
+      mark_slot(c, 0, st);
       return TFMM_OK;
     }
     (void)hipGraphExecDestroy(e.x);
@@ -1226,6 +1433,7 @@ tfmm_status tfmm_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32
   // same launch sequence on the capture stream for later calls
   s = translate_contiguous(c, op, A, B, nrhs, st, 0);
   if (s != TFMM_OK) return s;
+  mark_slot(c, 0, st);
   const unsigned gen = c->scratch_gen[0];
   HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
   s = translate_contiguous(c, op, A, B, nrhs, c->cap_stream, 0);
@@ -1308,6 +1516,14 @@ tfmm_status tfmm_wait(tfmm_ctx c, tfmm_ticket t, tfmm_status* job_status, double
   }
   if (job_status) *job_status = j->status;
   if (latency_us) *latency_us = (j->t_done - j->t_submit) * 1e6;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_sched_stats(tfmm_ctx c, uint64_t* out, size_t cap) {
+  if (!c || !out) return fail(TFMM_ERR_INVALID_ARG, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lk(c->qmu);
+  const uint64_t v[5] = {c->n_launch, c->n_parked, c->n_done, c->n_failed, (uint64_t)c->queue.size()};
+  for (size_t i = 0; i < cap && i < 5; ++i) out[i] = v[i];
   return TFMM_OK;
 }
 
@@ -1409,6 +1625,7 @@ tfmm_status tfmm_autotune(tfmm_ctx c, tfmm_op op, int32_t nrhs, int32_t reps, in
       ok = ok && translate_contiguous(c, op, A, B, nrhs, st, 0) == TFMM_OK;
       ok = ok && hipEventRecord(ev[2 * r + 1], st) == hipSuccess;
     }
+    if (ok) mark_slot(c, 0, st);
     if (!ok || hipStreamSynchronize(st) != hipSuccess) {
       (void)hipGetLastError();
       continue;

@@ -18,12 +18,22 @@
 namespace tfmm {
 
 // ---------------------------------------------------------------------------
-// Setup: Eq. (7) in FP64.  h_l^(2) by upward recurrence from the closed forms
-// of h_0 and h_1 (the recurrence is stable for the dominant y_l part), P_l by
-// Bonnet's recurrence.  Near offsets and the unused slot m_i = K_i are zero.
+// Setup: Eq. (7) in FP64 for a real or complex wavenumber k (a lossy medium,
+// Section III-A-5, has Im k < 0 under the e^{jwt} convention of Section II-A,
+// so e^{-jkR} decays).  h_l^(2)(z), z = k|R|, by upward recurrence
+// h_{l+1} = (2l+1)/z h_l - h_{l-1} from the closed forms h_0 = i e^{-iz}/z and
+// h_1 = e^{-iz} (i/z^2 - 1/z) (the recurrence is stable for the dominant y_l
+// part), P_l by Bonnet's recurrence.  Near offsets and the unused slot m_i = K_i
+// are zero.
 // ---------------------------------------------------------------------------
+struct cplx64 {
+  double r, i;
+};
+__device__ inline cplx64 cmul64(cplx64 a, cplx64 b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+
 __global__ void k_sample(double2* __restrict__ T, const double* __restrict__ khat, int K1, int K2, int K3,
-                         double box, double k, int L, int near_rule, double near_param, double sre, double sim) {
+                         double box, double kre, double kim, int L, int near_rule, double near_param, double sre,
+                         double sim) {
   const int n1 = 2 * K1, n2 = 2 * K2, n3 = 2 * K3;
   const long long N = (long long)n1 * n2 * n3;
   const long long m = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,38 +57,45 @@ __global__ void k_sample(double2* __restrict__ T, const double* __restrict__ kha
     if (!near) {
       const double Rx = box * d1, Ry = box * d2, Rz = box * d3;
       const double r = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
-      const double x = k * r;
+      const cplx64 z = {kre * r, kim * r};
       const double c = (khat[3 * p] * Rx + khat[3 * p + 1] * Ry + khat[3 * p + 2] * Rz) / r;
+      // e^{-iz} = e^{Im z} (cos Re z - i sin Re z)
       double sx, cx;
-      sincos(x, &sx, &cx);
-      // e^{-ix} = cx - i sx
-      // h0 = i e^{-ix}/x = (sx + i cx)/x ; h1 = e^{-ix}(i/x^2 - 1/x)
-      double h0r = sx / x, h0i = cx / x;
-      const double ar = -1.0 / x, ai = 1.0 / (x * x);  // (i/x^2 - 1/x)
-      double h1r = cx * ar + sx * ai, h1i = cx * ai - sx * ar;
+      sincos(z.r, &sx, &cx);
+      const double g = exp(z.i);
+      const cplx64 E = {g * cx, -g * sx};
+      const double zz = z.r * z.r + z.i * z.i;
+      const cplx64 u = {z.r / zz, -z.i / zz};  // 1/z
+      const cplx64 iu = {-u.i, u.r};           // i/z
+      const cplx64 h0 = cmul64(E, iu);
+      const cplx64 u2 = cmul64(u, iu);         // i/z^2
+      const cplx64 h1 = cmul64(E, {u2.r - u.r, u2.i - u.i});
       double P0 = 1.0, P1 = c;
-      // l = 0 term: h0 * P0
-      double sr = h0r * P0, si = h0i * P0;
-      if (L >= 1) {  // (-i)^1 * 3 * h1 * P1
-        sr += 3.0 * P1 * h1i;
-        si += -3.0 * P1 * h1r;
+      // l = 0 term: h0 P0; l = 1 term: (-i) 3 h1 P1
+      double sr = h0.r, si = h0.i;
+      if (L >= 1) {
+        sr += 3.0 * P1 * h1.i;
+        si += -3.0 * P1 * h1.r;
       }
-      double hmr = h0r, hmi = h0i, hr = h1r, hi = h1i;
+      cplx64 hm = h0, h = h1;
       for (int l = 1; l < L; ++l) {
         // advance to l+1
-        const double f = (2.0 * l + 1.0) / x;
-        const double nr = f * hr - hmr, ni = f * hi - hmi;
-        hmr = hr; hmi = hi; hr = nr; hi = ni;
+        const cplx64 fu = {(2.0 * l + 1.0) * u.r, (2.0 * l + 1.0) * u.i};
+        const cplx64 t = cmul64(fu, h);
+        const cplx64 nh = {t.r - hm.r, t.i - hm.i};
+        hm = h;
+        h = nh;
         const double P2 = ((2.0 * l + 1.0) * c * P1 - l * P0) / (l + 1.0);
-        P0 = P1; P1 = P2;
+        P0 = P1;
+        P1 = P2;
         const int lp = l + 1;
         const double wgt = (2.0 * lp + 1.0) * P1;
         // (-i)^lp
         switch (lp & 3) {
-          case 0: sr += wgt * hr; si += wgt * hi; break;
-          case 1: sr += wgt * hi; si -= wgt * hr; break;
-          case 2: sr -= wgt * hr; si -= wgt * hi; break;
-          default: sr -= wgt * hi; si += wgt * hr; break;
+          case 0: sr += wgt * h.r; si += wgt * h.i; break;
+          case 1: sr += wgt * h.i; si -= wgt * h.r; break;
+          case 2: sr -= wgt * h.r; si -= wgt * h.i; break;
+          default: sr -= wgt * h.i; si += wgt * h.r; break;
         }
       }
       out = make_double2(sre * sr - sim * si, sre * si + sim * sr);
@@ -87,11 +104,12 @@ __global__ void k_sample(double2* __restrict__ T, const double* __restrict__ kha
   T[(long long)p * N + m] = out;
 }
 
-hipError_t launch_sample(double2* T, const double* khat, int ndir, const int K[3], double box, double k, int L,
-                         int near_rule, double near_param, double sre, double sim, hipStream_t st) {
+hipError_t launch_sample(double2* T, const double* khat, int ndir, const int K[3], double box, double kre,
+                         double kim, int L, int near_rule, double near_param, double sre, double sim,
+                         hipStream_t st) {
   const long long N = 8LL * K[0] * K[1] * K[2];
   dim3 grid((unsigned)((N + 255) / 256), (unsigned)ndir);
-  hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, st, T, khat, K[0], K[1], K[2], box, k, L, near_rule,
+  hipLaunchKernelGGL(k_sample, grid, dim3(256), 0, st, T, khat, K[0], K[1], K[2], box, kre, kim, L, near_rule,
                      near_param, sre, sim);
   return hipGetLastError();
 }

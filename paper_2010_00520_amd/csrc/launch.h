@@ -96,9 +96,11 @@ struct GOp {
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                         long long csb, hipStream_t st);
 
-// FP64 operator sampling, Eq. (7): T[p][m1][m2][m3] (double2) for every direction.
-hipError_t launch_sample(double2* T, const double* khat, int ndir, const int K[3], double box, double k, int L,
-                         int near_rule, double near_param, double scale_re, double scale_im, hipStream_t st);
+// FP64 operator sampling, Eq. (7): T[p][m1][m2][m3] (double2) for every direction,
+// wavenumber k = kre + i kim.
+hipError_t launch_sample(double2* T, const double* khat, int ndir, const int K[3], double box, double kre,
+                         double kim, int L, int near_rule, double near_param, double scale_re, double scale_im,
+                         hipStream_t st);
 
 // Pack complex64 FULL operator [p][n1 n2 n3] into the [p][n3/2][nq] float4 layout.
 hipError_t launch_pack_full(const float2* src, float4* dst, int ndir, int nq, int n3, hipStream_t st);

@@ -38,11 +38,14 @@ class Problem(ctypes.Structure):
     _fields_ = [
         ("K", ctypes.c_int32 * 3),
         ("box_size", ctypes.c_double),
-        ("k", ctypes.c_double),
+        ("k_re", ctypes.c_double),
+        ("k_im", ctypes.c_double),
         ("L", ctypes.c_int32),
         ("digits", ctypes.c_double),
         ("n_theta", ctypes.c_int32),
         ("n_phi", ctypes.c_int32),
+        ("dirs", ctypes.POINTER(ctypes.c_double)),
+        ("n_dir", ctypes.c_int32),
         ("near_rule", ctypes.c_int),
         ("near_param", ctypes.c_double),
         ("scale_re", ctypes.c_double),
@@ -64,6 +67,7 @@ class OpInfo(ctypes.Structure):
         ("bytes_full", ctypes.c_size_t),
         ("bytes_stored", ctypes.c_size_t),
         ("elems_stored", ctypes.c_size_t),
+        ("bytes_scratch", ctypes.c_size_t),
         ("rel_err_fro", ctypes.c_double),
         ("max_dir_rel_err", ctypes.c_double),
         ("ranks", ctypes.c_int32 * 8),
@@ -74,7 +78,7 @@ class OpInfo(ctypes.Structure):
         return {
             "fmt": FORMAT_NAMES.get(self.fmt, self.fmt), "prec": self.prec, "K": tuple(self.K), "n": tuple(self.n),
             "n_dir": self.n_dir, "L": self.L, "bytes_full": self.bytes_full, "bytes_stored": self.bytes_stored,
-            "elems_stored": self.elems_stored, "rel_err_fro": self.rel_err_fro,
+            "elems_stored": self.elems_stored, "bytes_scratch": self.bytes_scratch, "rel_err_fro": self.rel_err_fro,
             "max_dir_rel_err": self.max_dir_rel_err, "ranks": tuple(self.ranks),
             "setup_seconds": self.setup_seconds,
         }
@@ -108,6 +112,7 @@ SIGNATURES = [
     ("tfmm_autotune", _ST, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                             ctypes.POINTER(ctypes.c_double)]),
     ("tfmm_op_plan", _ST, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t]),
+    ("tfmm_sched_stats", _ST, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t]),
 ]
 
 _lib = None
@@ -135,14 +140,24 @@ def _check(status: int):
 
 
 def make_problem(K, box=0.5, k=2 * np.pi, L=0, digits=0.0, fmt="full", tol=1e-4, prec="fp32", near="cheb",
-                 near_param=0.0, n_theta=0, n_phi=0, scale=1.0 + 0j) -> Problem:
+                 near_param=0.0, n_theta=0, n_phi=0, scale=1.0 + 0j, dirs=None, n_dir=0) -> Problem:
+    """tfmm_problem from keyword arguments.  `k` may be complex (lossy medium,
+    Im k < 0); `dirs` an (n_dir, 3) array of unit vectors replacing the direction
+    grid (the returned Problem keeps a reference to its buffer)."""
     p = Problem()
     p.K[:] = [int(x) for x in K]
     p.box_size = float(box)
-    p.k = float(k)
+    p.k_re, p.k_im = float(np.real(k)), float(np.imag(k))
     p.L = int(L)
     p.digits = float(digits)
     p.n_theta, p.n_phi = int(n_theta), int(n_phi)
+    if dirs is not None:
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        p._dirs_keep = d
+        p.dirs = d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.n_dir = d.shape[0]
+    else:
+        p.n_dir = int(n_dir)
     p.near_rule = NEAR[near]
     p.near_param = float(near_param)
     p.scale_re, p.scale_im = float(np.real(scale)), float(np.imag(scale))
@@ -173,6 +188,19 @@ class Operator:
     def __init__(self, ctx: "Context", handle: int):
         self.ctx = ctx
         self.handle = ctypes.c_void_p(handle)
+        inf = self.info()
+        # per-RHS block shape of A and B: (n_dir, Kx, Ky, Kz)
+        self.block = (inf["n_dir"],) + tuple(inf["K"])
+
+    def check_io(self, A, B) -> int:
+        """Raise unless A and B are [nrhs, n_dir, Kx, Ky, Kz] complex64 device tensors
+        of this operator with the same nrhs; returns nrhs."""
+        for name, t in (("A", A), ("B", B)):
+            if tuple(t.shape[1:]) != self.block or t.dim() != 5:
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, operator needs [nrhs, {', '.join(map(str, self.block))}]")
+        if A.shape[0] != B.shape[0] or A.shape[0] < 1:
+            raise ValueError("A and B must hold the same number (>= 1) of right-hand sides")
+        return int(A.shape[0])
 
     def info(self) -> dict:
         inf = OpInfo()
@@ -214,11 +242,13 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib.tfmm_ctx_create(int(device), int(budget_bytes), ctypes.byref(h)))
         self.handle = h
+        self._live = {}  # ticket -> (A, B) of submitted jobs not yet reported done
 
     def close(self):
         if self.handle:
             _check(load().tfmm_ctx_destroy(self.handle))
             self.handle = ctypes.c_void_p(0)
+            self._live.clear()
 
     def __enter__(self):
         return self
@@ -238,8 +268,8 @@ class Context:
         return Operator(self, h.value)
 
     def import_factors(self, K, L, fmt: str, ranks: Sequence[int], data: np.ndarray, prec="fp32", n_theta=0,
-                       n_phi=0) -> Operator:
-        prob = make_problem(K, L=L, fmt=fmt, prec=prec, n_theta=n_theta, n_phi=n_phi)
+                       n_phi=0, n_dir=0) -> Operator:
+        prob = make_problem(K, L=L, fmt=fmt, prec=prec, n_theta=n_theta, n_phi=n_phi, n_dir=n_dir)
         r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32).ravel())
         d = np.ascontiguousarray(np.asarray(data, dtype=np.complex128).ravel()).view(np.float64)
         h = ctypes.c_void_p()
@@ -250,24 +280,37 @@ class Context:
 
     def translate(self, op: Operator, A, B, stream=None):
         """Enqueue B = translate(A) on `stream` (torch stream; default: current)."""
-        nrhs = int(A.shape[0])
+        nrhs = op.check_io(A, B)
         _check(load().tfmm_translate(self.handle, op.handle, ctypes.c_void_p(_dev_ptr(A)),
                                      ctypes.c_void_p(_dev_ptr(B)), nrhs, ctypes.c_void_p(_stream_handle(stream))))
 
     def submit(self, op: Operator, A, B) -> int:
+        """Queue a job for the scheduler.  The scheduler's streams do not wait for
+        torch's, so the current stream is synchronised first (A must be complete
+        when the job is submitted); A and B are kept alive until poll or wait
+        reports the job done."""
+        import torch
+
+        nrhs = op.check_io(A, B)
+        a, b = _dev_ptr(A), _dev_ptr(B)
+        torch.cuda.current_stream().synchronize()
         t = ctypes.c_uint64()
-        _check(load().tfmm_submit(self.handle, op.handle, ctypes.c_void_p(_dev_ptr(A)), ctypes.c_void_p(_dev_ptr(B)),
-                                  int(A.shape[0]), ctypes.byref(t)))
+        _check(load().tfmm_submit(self.handle, op.handle, ctypes.c_void_p(a), ctypes.c_void_p(b), nrhs,
+                                  ctypes.byref(t)))
+        self._live[t.value] = (A, B)
         return t.value
 
     def poll(self, ticket: int):
         done, st, lat = ctypes.c_int32(), ctypes.c_int(), ctypes.c_double()
         _check(load().tfmm_poll(self.handle, ticket, ctypes.byref(done), ctypes.byref(st), ctypes.byref(lat)))
+        if done.value:
+            self._live.pop(ticket, None)
         return bool(done.value), st.value, lat.value
 
     def wait(self, ticket: int):
         st, lat = ctypes.c_int(), ctypes.c_double()
         _check(load().tfmm_wait(self.handle, ticket, ctypes.byref(st), ctypes.byref(lat)))
+        self._live.pop(ticket, None)
         return st.value, lat.value
 
     def autotune(self, op: "Operator", nrhs: int = 1, reps: int = 20):
@@ -277,6 +320,12 @@ class Context:
         ms = ctypes.c_double()
         _check(load().tfmm_autotune(self.handle, op.handle, int(nrhs), int(reps), ch, ctypes.byref(ms)))
         return {"fused": bool(ch[0]), "cb": int(ch[1]), "register_chained": bool(ch[2])}, ms.value
+
+    def sched_stats(self) -> dict:
+        """Scheduler counters: launches, memory waits, jobs done, jobs failed, queued."""
+        v = (ctypes.c_uint64 * 5)()
+        _check(load().tfmm_sched_stats(self.handle, v, 5))
+        return dict(zip(("launches", "memory_waits", "done", "failed", "queued"), (int(x) for x in v)))
 
     def set_profiling(self, on: bool):
         _check(load().tfmm_set_profiling(self.handle, 1 if on else 0))

@@ -75,7 +75,7 @@ class Workload:
 # The five workloads the measurements are quoted on (index 0..4).
 TINY = Workload("tiny-4^3", (4, 4, 4), 0.5, 5, fmt="tucker3d", tol=1e-6, nrhs=1, seed=SEED_BASE + 0)
 PLAIN = Workload("plain-16^3", (16, 16, 16), 0.5, 10, fmt="tucker3d", tol=1e-4, nrhs=1, seed=SEED_BASE + 1)
-BATCHING = Workload("batching-24^3", (24, 24, 24), 0.25, 8, fmt="tt3d", tol=1e-4, nrhs=8, seed=SEED_BASE + 2)
+BATCHING = Workload("batching-24^3", (24, 24, 24), 0.25, 8, fmt="tucker4d", tol=1e-4, nrhs=8, seed=SEED_BASE + 2)
 PRECISION = Workload("precision-128x8x8", (128, 8, 8), 0.5, 12, fmt="htucker4d", tol=1e-4, nrhs=4,
                      seed=SEED_BASE + 3)
 SERVING_GRIDS = ((8, 8, 8), (12, 12, 12), (16, 16, 16), (24, 24, 24), (32, 32, 32), (64, 16, 16))

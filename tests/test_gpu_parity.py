@@ -310,24 +310,51 @@ def test_lds_staged_tucker_restoration(fmt, no_fused, prec):
     c.close()
 
 
+@pytest.mark.parametrize("eps", [1.0, 2 - 1j, 2 - 8j])
 @pytest.mark.parametrize("K,L", [((4, 4, 4), 5), ((64, 4, 4), 14)])
-def test_fp64_sampler_matches_oracle(ctx, K, L):
+def test_fp64_sampler_matches_oracle(ctx, K, L, eps):
     """FP64 operator sampling on the device (Eq. (7), readings R1-R3), then the host
     FP64 FFT: the uncompressed operator read back with tfmm_op_export must match the
     oracle's sampled and FFT'ed operator to 1e-12 relative (the FP64 rounding level of
     the spherical-Hankel and Legendre recurrences), and its inverse FFT the spatial
     samples, both per direction.  64 x 4 x 4 boxes at L = 14 reach l > kR for every
-    offset, where an unstable recurrence for h_l would show."""
+    offset, where an unstable recurrence for h_l would show.  Lossy media (Section
+    III-A-5, Table IV permittivities) give a complex wavenumber k = k0 sqrt(eps_r):
+    at eps_r = 2 - 8j the far samples decay by up to e^-355."""
     w = synth.TINY.with_(K=K, L=L)
-    op = ctx.setup(K=K, box=w.box, k=w.k, L=L, fmt="full")
+    k = w.k * np.sqrt(complex(eps)) if eps != 1.0 else w.k
+    op = ctx.setup(K=K, box=w.box, k=k, L=L, fmt="full")
     n = tuple(2 * k for k in K)
     got = op.export().reshape((w.n_dir,) + n)
     op.release()
     khat, _ = O.directions(L)
-    T = O.sample_operator(K, w.box, w.k, L, khat)
+    T = O.sample_operator(K, w.box, k, L, khat)
     That = O.fft_operator(T)
     assert O.rel_l2(got, That) <= 1e-12
     spatial = np.fft.ifftn(got, axes=(-3, -2, -1))
     for p in range(w.n_dir):
         assert O.rel_l2(got[p], That[p]) <= 1e-12, p
         assert O.rel_l2(spatial[p], T[p]) <= 1e-12, p
+
+
+@pytest.mark.parametrize("fmt", ["tucker3d", "htucker4d", "tt4d"])
+def test_lossy_medium_translation(ctx, fmt):
+    """Section III-A-5: translation in a lossy medium (eps_r = 2 - 2j, complex
+    wavenumber) through the compressed operator matches the exact FP64 translation
+    within 10 gamma + 1e-6, and the loss lowers the stored memory against the same
+    grid in the lossless medium eps_r = 2 (Table IV trend)."""
+    K, L, tol = (8, 8, 8), 10, 1e-4
+    w = synth.TINY.with_(K=K, L=L)
+    k_loss = w.k * np.sqrt(2 - 2j)
+    op = ctx.setup(K=K, box=0.5, k=k_loss, L=L, fmt=fmt, tol=tol)
+    lossless = ctx.setup(K=K, box=0.5, k=w.k * np.sqrt(2.0), L=L, fmt=fmt, tol=tol)
+    assert op.info()["bytes_stored"] < lossless.info()["bytes_stored"]
+    lossless.release()
+    A = synth.patterns_for(w, nrhs=2)
+    got = gpu_translate(ctx, op, A)
+    op.release()
+    khat, _ = O.directions(L)
+    for p in (0, 17, 101, w.n_dir - 1):
+        Th = O.fft_operator(O.sample_operator(K, 0.5, k_loss, L, khat[p:p + 1]))
+        ref = O.translate_fft(A[:, p:p + 1].astype(np.complex128), Th)
+        assert O.rel_l2(got[:, p:p + 1], ref) <= 10 * tol + 1e-6, p

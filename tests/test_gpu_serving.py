@@ -120,3 +120,54 @@ def test_release_after_jobs_complete(P):
     if not released:
         op.release()
     ctx.close()
+
+
+def test_jobs_park_for_memory_and_match_solo(P):
+    """Memory-based admission: with a budget that holds the operator and one
+    job's A and B (not two), jobs submitted together wait for memory at the head
+    of the queue instead of failing, complete in order, and each result is
+    bitwise the result of the job run alone.  A job that cannot fit even with
+    nothing else running fails with TFMM_ERR_BUDGET and leaves the queue moving.
+    The operator takes the fused path (16^3 FFT grid), which needs no
+    translation scratch, so a job's charge is exactly its A and B."""
+    fmt, K, L = "tucker3d", (8, 8, 8), 3
+    n = tuple(2 * k for k in K)
+    ndir = (L + 1) * 2 * (L + 1)
+    rk, data, _ = random_factors(fmt, n, ndir, np.random.default_rng(5))
+    nrhs = 4
+    jobs = [torch.from_numpy(synth.gaussian_patterns((nrhs, ndir) + K, 300 + j)).cuda() for j in range(6)]
+    io = 2 * jobs[0].numel() * 8
+    # solo results and the memory the operator takes, in a context with the default budget
+    with P.Context(0) as big:
+        op = big.import_factors(K, L, fmt, rk, data)
+        assert op.plan()["fused"] and op.info()["bytes_scratch"] == 0
+        u0, _ = big.memory()
+        solo = []
+        for A in jobs:
+            B = torch.zeros_like(A)
+            big.translate(op, A, B)
+            solo.append(B)
+        torch.cuda.synchronize()
+        op.release()
+    with P.Context(0, budget_bytes=u0 + int(1.5 * io)) as ctx:
+        op = ctx.import_factors(K, L, fmt, rk, data)
+        outs = [torch.zeros_like(A) for A in jobs]
+        torch.cuda.synchronize()
+        tickets = [ctx.submit(op, A, B) for A, B in zip(jobs, outs)]
+        # a job four times as large can never fit next to the operator
+        Abig = torch.cat([jobs[0]] * 4)
+        tbig = ctx.submit(op, Abig, torch.zeros_like(Abig))
+        tafter = ctx.submit(op, jobs[1], torch.zeros_like(jobs[1]))
+        for t in tickets:
+            st, lat = ctx.wait(t)
+            assert st == 0 and lat > 0
+        st_big, _ = ctx.wait(tbig)
+        st_after, _ = ctx.wait(tafter)
+        stats = ctx.sched_stats()
+        assert (st_big, st_after) == (3, 0), (st_big, st_after, stats)
+        assert stats["memory_waits"] >= 1 and stats["failed"] == 1 and stats["done"] == 7, stats
+        used, budget = ctx.memory()
+        assert used <= budget
+        for j, (B, R) in enumerate(zip(outs, solo)):
+            assert torch.equal(B, R), f"parked job {j} differs from its solo run"
+        op.release()
