@@ -1003,18 +1003,21 @@ void worker_loop(tfmm_ctx c) {
           }
         }
       }
-      if (!park && adm == TFMM_OK) {
-        // jobs beyond `keep` go back to the head of the queue, in order
+      if (!park) {
+        // jobs beyond `keep` (all but the oldest when it cannot fit) go back to
+        // the head of the queue, in order
+        if (adm != TFMM_OK) keep = 1;
         std::vector<std::shared_ptr<Job>> back(batch.begin() + keep, batch.end());
         batch.resize(keep);
         if (!back.empty()) {
           std::lock_guard<std::mutex> lk(c->qmu);
           c->queue.insert(c->queue.begin(), back.begin(), back.end());
         }
-        for (auto& j : batch) {
-          j->charged = job_io_bytes(*j);
-          c->used += j->charged;
-        }
+        if (adm == TFMM_OK)
+          for (auto& j : batch) {
+            j->charged = job_io_bytes(*j);
+            c->used += j->charged;
+          }
       }
     }
     if (park) {
