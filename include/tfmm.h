@@ -230,6 +230,30 @@ tfmm_status tfmm_op_release(tfmm_ctx ctx, tfmm_op op);
 tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
                            void* hip_stream);
 
+/* ---- translation without device allocation -------------------------------- */
+
+/* Bytes of the fixed device scratch of tfmm_translate_noalloc (per device). */
+#define TFMM_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * translation as tfmm_translate, enqueued on `hip_stream`, with every byte of
+ * scratch taken from a fixed device array of TFMM_NOALLOC_SCRATCH_BYTES that
+ * the library holds on each device it runs on until the process ends (its
+ * address is looked up at context creation).  The call makes no hipMalloc or
+ * hipFree and no allocating library call, and never captures or replays a
+ * graph (so it may itself be captured).  The direction chunk of the three-pass
+ * pipeline shrinks until the scratch fits; a translation that does not fit
+ * even with one direction per chunk (the per-direction cores of a 4-D format
+ * plus one direction's half spectrum and z-major copies for all RHS) fails
+ * with TFMM_ERR_UNSUPPORTED before any work is enqueued.  Every call on a
+ * device shares that device's array, which keeps the last call's contents:
+ * calls that overlap on one device (other streams, other threads, other
+ * contexts) race and must be serialised by the caller.  Operators, A and B as
+ * for tfmm_translate; the tile plan is the operator's current one. */
+tfmm_status tfmm_translate_noalloc(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
+                                   void* hip_stream);
+
 /* ---- serving: continuous batching (submit / poll) ------------------------ */
 
 /* Queue a translation job for the context's scheduler thread (continuous

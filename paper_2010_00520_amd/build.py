@@ -23,7 +23,7 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
-DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tt3d", "zstage_tt4d")
+DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tt3d", "zstage_tt4d", "noalloc")
 
 
 def _run(cmd):

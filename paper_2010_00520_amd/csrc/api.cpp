@@ -21,6 +21,7 @@
 
 #include "host_math.h"
 #include "launch.h"
+#include "noalloc.h"
 #include "tfmm.h"
 
 using tfmm::cd;
@@ -192,6 +193,7 @@ struct tfmm_ctx_s {
   // wait for memory, jobs completed and jobs failed
   uint64_t n_launch = 0, n_parked = 0, n_done = 0, n_failed = 0;
   std::vector<tfmm_op> ops;
+  std::string noalloc_error;           // why the fixed scratch is unavailable (empty: available)
 };
 
 // ---------------------------------------------------------------------------
@@ -1173,6 +1175,16 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   if (ng && ng[0] == '1') c->graph_mode = 0;
   if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->ncu < 1)
     c->ncu = 1;
+  // device address of this device's copy of the allocation-free entry point's
+  // fixed scratch (looked up once per device; the device is current here)
+  {
+    const hipError_t e = tfmm::noalloc_scratch_init(device);
+    if (e != hipSuccess) {
+      // only the allocation-free entry point needs it; it reports this error
+      c->noalloc_error = std::string("fixed scratch lookup failed: ") + hipGetErrorString(e);
+      (void)hipGetLastError();
+    }
+  }
   if (hipMalloc((void**)&c->counters, 64 * sizeof(int)) != hipSuccess ||
       hipMemset(c->counters, 0, 64 * sizeof(int)) != hipSuccess ||
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -1460,6 +1472,41 @@ tfmm_status tfmm_translate(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32
   }
   G.push_back({nrhs, A, B, gen, gr, x});
   return TFMM_OK;
+}
+
+tfmm_status tfmm_translate_noalloc(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs, void* stream) {
+  tfmm_status s = check_translate(c, op, A, B, nrhs);
+  if (s != TFMM_OK) return s;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  char* base = (char*)tfmm::noalloc_scratch(c->device);
+  if (!base)
+    return fail(TFMM_ERR_HIP, c->noalloc_error.empty() ? "fixed scratch of this device was not looked up"
+                                                        : c->noalloc_error);
+  const size_t room = tfmm::kNoAllocScratchBytes - tfmm::kNoAllocCounterBytes;
+  // the direction chunk shrinks (down to one direction) until the scratch fits
+  size_t cap = c->hcap;
+  ScratchPlan sp = scratch_plan(op, nrhs, cap);
+  while (sp.total() > room && sp.ndl > 1) {
+    cap /= 2;
+    sp = scratch_plan(op, nrhs, cap);
+  }
+  if (sp.total() > room)
+    return fail(TFMM_ERR_UNSUPPORTED, "translation needs " + std::to_string(sp.total()) +
+                                          " B of scratch, the fixed scratch holds " + std::to_string(room) + " B");
+  hipStream_t st = (hipStream_t)stream;
+  int* counter = (int*)base;
+  // the persistent launches need their counters at zero; a kernel (not a
+  // memset) so that the call may be captured
+  HIP_TRY(tfmm::launch_zero(counter, 2, st));
+  const size_t blk = (size_t)op->ndir * op->K[0] * op->K[1] * op->K[2];
+  std::vector<const float2*> As(nrhs);
+  std::vector<float2*> Bs(nrhs);
+  for (int i = 0; i < nrhs; ++i) {
+    As[i] = (const float2*)A + i * blk;
+    Bs[i] = (float2*)B + i * blk;
+  }
+  return enqueue_translate(c, op, As, Bs, st, base + tfmm::kNoAllocCounterBytes, sp, counter, false);
 }
 
 tfmm_status tfmm_submit(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs, tfmm_ticket* out) {

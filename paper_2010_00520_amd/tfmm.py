@@ -100,6 +100,7 @@ SIGNATURES = [
     ("tfmm_op_export", _ST, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     ("tfmm_op_release", _ST, [_VP, _VP]),
     ("tfmm_translate", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    ("tfmm_translate_noalloc", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
     ("tfmm_submit", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     ("tfmm_poll", _ST, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
                         ctypes.POINTER(ctypes.c_double)]),
@@ -283,6 +284,14 @@ class Context:
         nrhs = op.check_io(A, B)
         _check(load().tfmm_translate(self.handle, op.handle, ctypes.c_void_p(_dev_ptr(A)),
                                      ctypes.c_void_p(_dev_ptr(B)), nrhs, ctypes.c_void_p(_stream_handle(stream))))
+
+    def translate_noalloc(self, op: Operator, A, B, stream=None):
+        """tfmm_translate_noalloc: the same translation with the library's fixed
+        device scratch (no device allocation; calls on one device must not overlap)."""
+        nrhs = op.check_io(A, B)
+        _check(load().tfmm_translate_noalloc(self.handle, op.handle, ctypes.c_void_p(_dev_ptr(A)),
+                                             ctypes.c_void_p(_dev_ptr(B)), nrhs,
+                                             ctypes.c_void_p(_stream_handle(stream))))
 
     def submit(self, op: Operator, A, B) -> int:
         """Queue a job for the scheduler.  The scheduler's streams do not wait for
