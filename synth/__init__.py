@@ -118,3 +118,40 @@ def serving_requests(count: int, seed: int = SERVING_SEED, rate_hz: float = SERV
         out.append({"id": i, "arrival_s": t, "grid": grid, "fmt": fmt, "nrhs": nrhs,
                     "seed": seed * 1000 + i})
     return out
+
+
+# ---------------------------------------------------------------------------
+# Basis functions of the far-field matvec (aggregation, Eq. (4); projection,
+# Eq. (6)): point dipoles with seeded positions and unit orientations.
+# ---------------------------------------------------------------------------
+
+def dipoles_near_centres(K, box: float, n: int, seed: int, spread: float = 0.25):
+    """n dipoles in random boxes of the grid, each within +-spread*box of its box
+    centre per axis; returns (pos (n, 3), orient (n, 3) unit vectors)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = np.stack([rng.integers(0, k, n) for k in K], axis=1)
+    pos = (v + 0.5) * box + rng.uniform(-spread, spread, (n, 3)) * box
+    u = rng.standard_normal((n, 3))
+    return pos, u / np.linalg.norm(u, axis=1, keepdims=True)
+
+
+def sphere_dipoles(K, box: float, n: int, seed: int, radius_frac: float = 0.45):
+    """n dipoles on a sphere centred in the box grid (radius radius_frac times the
+    smallest grid extent), oriented tangentially at random: a stand-in for the
+    RWG basis of a scattering surface (only boxes the surface crosses are
+    non-empty).  Returns (pos (n, 3), orient (n, 3))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ext = np.asarray(K, dtype=np.float64) * box
+    c = ext / 2
+    R = radius_frac * ext.min()
+    x = rng.standard_normal((n, 3))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    t = rng.standard_normal((n, 3))
+    t -= np.sum(t * x, axis=1, keepdims=True) * x
+    t /= np.linalg.norm(t, axis=1, keepdims=True)
+    return c + R * x, t
+
+
+def current_vector(n: int, nrhs: int, seed: int) -> np.ndarray:
+    """Basis-function coefficients I (nrhs, n), complex64 Gaussian."""
+    return gaussian_patterns((nrhs, n), seed)
