@@ -46,6 +46,8 @@ extern "C" {
 
 typedef struct tfmm_ctx_s* tfmm_ctx;
 typedef struct tfmm_op_s* tfmm_op;
+typedef struct tfmm_basis_s* tfmm_basis;
+typedef struct tfmm_near_s* tfmm_near;
 typedef uint64_t tfmm_ticket;
 
 typedef enum {
@@ -59,7 +61,8 @@ typedef enum {
   TFMM_ERR_UNKNOWN_TICKET = 7,
   TFMM_ERR_QUEUE_FULL = 8,
   TFMM_ERR_INTERNAL = 9,
-  TFMM_ERR_NO_DEVICE = 10    /* no HIP device (the library has no CPU fallback)    */
+  TFMM_ERR_NO_DEVICE = 10,   /* no HIP device (the library has no CPU fallback)    */
+  TFMM_ERR_NOT_CONVERGED = 11 /* an iterative solve stopped at its iteration limit */
 } tfmm_status;
 
 /* Operator storage formats (Section II-B). */
@@ -134,7 +137,9 @@ typedef struct {
                               per-direction cores of the 4-D formats, z-major
                               copies); it grows with the RHS count up to the
                               context's chunk size                                  */
-  double rel_err_fro;      /* ||T~ - T~hat||_F / ||T~||_F over all directions, FP64 at setup */
+  double rel_err_fro;      /* ||T~ - T~hat||_F / ||T~||_F over all directions, estimated at
+                              setup from ||T~||^2 - ||core||^2 in FP64 (below ~1e-6 the
+                              cancellation leaves it uncertain by about gamma)        */
   double max_dir_rel_err;  /* max over directions of the same ratio                  */
   int32_t ranks[8];        /* format ranks; 3-D formats: maximum over directions     */
   double setup_seconds;
@@ -245,7 +250,7 @@ tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int
  * graph (so it may itself be captured).  The direction chunk of the three-pass
  * pipeline shrinks until the scratch fits; a translation that does not fit
  * even with one direction per chunk (the per-direction cores of a 4-D format
- * plus one direction's half spectrum and z-major copies for all RHS) fails
+ * plus one direction's x-FFT'ed planes for all RHS) fails
  * with TFMM_ERR_UNSUPPORTED before any work is enqueued.  Every call on a
  * device shares that device's array, which keeps the last call's contents:
  * calls that overlap on one device (other streams, other threads, other
@@ -253,6 +258,71 @@ tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int
  * for tfmm_translate; the tile plan is the operator's current one. */
 tfmm_status tfmm_translate_noalloc(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
                                    void* hip_stream);
+
+/* ---- far-field matrix-vector product around the translation ---------------- */
+
+/* Basis functions of the far-field product (Section II-A): point dipoles
+ * b_n(r) = u_n delta(r - r_n) in the box grid of `op` (grid corner at the
+ * origin, box v = floor(r / a), centre (v + 1/2) a).  Their far-field patterns,
+ * Eq. (3) for a delta-function basis,
+ *     P+(k_p, b_n) = (I - k_p k_p) u_n exp(+jk k_p . (r_n - r_v)),
+ * kept as theta and phi components, are computed on the device in FP64 for
+ * every direction of `op` and stored as complex64 (16 B per direction and
+ * basis function); the receive patterns of Eq. (6) are
+ * P-(k_p, b_m) = (I - k_p k_p) u_m exp(-jk k_p . (r_m - r_v')), the conjugates
+ * of P+ for a real k.  `pos` and `orient` are host arrays n_basis x 3 (read
+ * during the call; orientations unit vectors).  The operator must come from
+ * tfmm_setup_compressed with a direction grid (its quadrature weights w_p are
+ * used); it stays referenced until tfmm_basis_release.  Charged to the budget. */
+tfmm_status tfmm_basis_setup(tfmm_ctx ctx, tfmm_op op, int32_t n_basis, const double* pos, const double* orient,
+                             tfmm_basis* out);
+tfmm_status tfmm_basis_release(tfmm_ctx ctx, tfmm_basis basis);
+
+/* Aggregation, Eq. (4): A_v(k_p) = sum_{n in box v} P+(k_p, b_n) I_n.
+ * I: device complex64 [nrhs][n_basis] (caller order); A: device complex64
+ * [2 nrhs][n_dir][Kx][Ky][Kz], field 2 r + c = component c (0 theta, 1 phi) of
+ * RHS r (each component is one right-hand side of tfmm_translate); empty boxes
+ * are written as zero.  Enqueued on `hip_stream`. */
+tfmm_status tfmm_aggregate(tfmm_ctx ctx, tfmm_basis basis, const void* I, void* A, int32_t nrhs, void* hip_stream);
+
+/* Projection with the direction quadrature, Eq. (6):
+ * y_m = sum_p w_p sum_c P-_c(k_p, b_m) B_c,v'(m)(k_p).  B: device complex64
+ * [2 nrhs][n_dir][Kx][Ky][Kz] as for tfmm_aggregate; y: device complex64
+ * [nrhs][n_basis].  Enqueued on `hip_stream`. */
+tfmm_status tfmm_disaggregate(tfmm_ctx ctx, tfmm_basis basis, const void* B, void* y, int32_t nrhs,
+                              void* hip_stream);
+
+/* The far-field part of the matrix-vector product of Eq. (2): aggregation,
+ * the translation of Eq. (5) through `op` (compressed or not), projection.
+ * I, y as above; `op` is the basis's operator.  The intermediate A and B
+ * (2 x 2 nrhs x n_dir x Kx x Ky x Kz complex64) are context scratch, charged to
+ * the budget and kept; calls on one context must not overlap on the device. */
+tfmm_status tfmm_farfield_matvec(tfmm_ctx ctx, tfmm_op op, tfmm_basis basis, const void* I, void* y, int32_t nrhs,
+                                 void* hip_stream);
+
+/* ---- iterative solution of Eq. (2) ---------------------------------------- */
+
+/* Near-field matrix of the system (the classically computed interactions of
+ * Section II-A; this library takes it as given): n x n, CSR on the host
+ * (row_ptr[n + 1], cols[nnz], vals[2 nnz] complex128 interleaved; read during
+ * the call), stored on the device as complex64.  Charged to the budget. */
+tfmm_status tfmm_near_setup(tfmm_ctx ctx, int32_t n, const int32_t* row_ptr, const int32_t* cols,
+                            const double* vals, tfmm_near* out);
+tfmm_status tfmm_near_release(tfmm_ctx ctx, tfmm_near near);
+/* y = Zn x for nrhs device complex64 vectors of n entries each (x, y [nrhs][n]). */
+tfmm_status tfmm_near_matvec(tfmm_ctx ctx, tfmm_near near, const void* x, void* y, int32_t nrhs, void* hip_stream);
+
+/* Solve (Zn + Zfar) I = V by TFQMR (transpose-free quasi-minimal residual,
+ * Section II-A), Zfar = tfmm_farfield_matvec of (op, basis).  V, I: device
+ * complex64 vectors of n_basis entries (I is written only on success).  The
+ * Krylov vectors are complex128 on the device; initial guess 0, shadow
+ * residual V.  Stops when ||V - Z I|| / ||V|| <= tol (checked whenever
+ * Freund's bound tau sqrt(m + 1) on the residual of half step m passes tol),
+ * else fails with TFMM_ERR_NOT_CONVERGED after maxit iterations (two products
+ * with Z each).  iters / relres (may be NULL) receive the iteration count and
+ * the last true relative residual.  Blocks until done; uses its own stream. */
+tfmm_status tfmm_solve_tfqmr(tfmm_ctx ctx, tfmm_op op, tfmm_basis basis, tfmm_near near, const void* V, void* I,
+                             double tol, int32_t maxit, int32_t* iters, double* relres);
 
 /* ---- serving: continuous batching (submit / poll) ------------------------ */
 

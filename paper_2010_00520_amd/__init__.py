@@ -3,5 +3,5 @@
 The compute path is libtfmm (HIP kernels for gfx950 behind the C ABI in
 include/tfmm.h); this package only builds it and binds it.
 """
-from .tfmm import (FORMATS, PRECISIONS, Context, Operator, Problem, TfmmError, load,  # noqa: F401
+from .tfmm import (FORMATS, PRECISIONS, Basis, Context, NearField, Operator, Problem, TfmmError, load,  # noqa: F401
                    make_problem, SIGNATURES)

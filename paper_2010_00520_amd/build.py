@@ -23,7 +23,9 @@ ARCH = "gfx950"
 # Packed FP32 instructions are disabled for all device code.
 NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
-DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tt3d", "zstage_tt4d", "noalloc")
+# host code calling the HIP runtime and ROCm libraries (operator setup, solver)
+HOST_HIP_UNITS = ("setup_gpu", "solver")
+DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tt3d", "zstage_tt4d", "noalloc", "setup_kernels", "xpass", "farfield")
 
 
 def _run(cmd):
@@ -43,15 +45,22 @@ def build(verbose: bool = False) -> str:
         [HIPCC, "--offload-arch=" + ARCH] + COMMON + NO_PK + ["-c", os.path.join(CSRC, "api.cpp"), "-o",
                                                              os.path.join(BUILD, "api.o")],
     ] + [
+        [HIPCC, "--offload-arch=" + ARCH] + COMMON + NO_PK + ["-c", os.path.join(CSRC, f + ".cpp"), "-o",
+                                                             os.path.join(BUILD, f + ".o")]
+        for f in HOST_HIP_UNITS
+    ] + [
         [HIPCC, "--offload-arch=" + ARCH] + COMMON + NO_PK + ["-c", os.path.join(CSRC, f + ".hip"), "-o",
                                                              os.path.join(BUILD, f + ".o")]
         for f in DEVICE_UNITS
     ]
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(_run, jobs))
-    objs = [os.path.join(BUILD, n + ".o") for n in ("host_math", "api") + DEVICE_UNITS]
+    objs = [os.path.join(BUILD, n + ".o") for n in ("host_math", "api") + HOST_HIP_UNITS + DEVICE_UNITS]
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs + ["-pthread"])
+    # hipFFT, rocBLAS and rocSOLVER serve the FP64 operator setup and the
+    # solver's FP64 vector operations
+    _run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs +
+         ["-pthread", "-L/opt/rocm/lib", "-lhipfft", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     if verbose:
         print("built", LIB)

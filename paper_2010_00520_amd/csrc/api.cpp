@@ -20,8 +20,10 @@
 #include <vector>
 
 #include "host_math.h"
+#include "internal.h"
 #include "launch.h"
 #include "noalloc.h"
+#include "setup_gpu.h"
 #include "tfmm.h"
 
 using tfmm::cd;
@@ -95,6 +97,12 @@ struct tfmm_op_s {
   int* d_perm = nullptr;               // direction order, costliest restoration first (NULL: identity)
   float2* d_roots_z = nullptr;         // exp(-2 pi i m / n3), m < n3 (context table)
   float2* d_roots_x = nullptr;         // exp(-2 pi i m / n1) when n1 > 64 (context table), else NULL
+  // physics of the problem (set by tfmm_setup_compressed from a direction grid):
+  // directions, quadrature weights, wavenumber and box size, for the far-field
+  // patterns of tfmm_basis_setup
+  bool physical = false;
+  std::vector<double> khat, wts;
+  double k_re = 0.0, k_im = 0.0, box = 0.0;
   // captured translations, keyed by (nrhs, A, B) and the scratch generation
   struct GraphEntry {
     int nrhs;
@@ -109,6 +117,27 @@ struct tfmm_op_s {
   bool tuned = false;                  // choice came from the autotuner or its cache
   tfmm_op_info info{};
   std::atomic<int> refs{0};
+};
+
+struct tfmm_near_s {
+  tfmm_ctx ctx = nullptr;
+  int n = 0;
+  long long nnz = 0;
+  int* d_rp = nullptr;                 // [n + 1]
+  int* d_ci = nullptr;                 // [nnz]
+  float2* d_val = nullptr;             // [nnz] complex64
+};
+
+struct tfmm_basis_s {
+  tfmm_ctx ctx = nullptr;
+  tfmm_op op = nullptr;                // operator whose directions and grid the patterns follow
+  int N = 0, nbox = 0, ndir = 0;
+  float4* d_pat = nullptr;             // [p][n] (theta.u, phi.u, Re e, Im e), sorted order
+  int* d_start = nullptr;              // [nbox + 1] sorted range of each box
+  int* d_orig = nullptr;               // [N] caller index of sorted basis n
+  int* d_boxof = nullptr;              // [N] box of sorted basis n
+  float* d_w = nullptr;                // [ndir] quadrature weights
+  size_t bytes = 0;
 };
 
 struct Job {
@@ -138,6 +167,7 @@ struct tfmm_ctx_s {
   int device = 0;
   bool no_fused = false;               // TFMM_NO_FUSED=1: always use the three-pass pipeline
   bool no_tk2 = false;                 // TFMM_NO_TK2=1: Tucker restoration through LDS-staged products
+  bool host_compress = false;          // TFMM_HOST_COMPRESS=1: compress the 4-D formats on the host
   size_t hcap = (size_t)256 << 20;     // three-pass half-spectrum chunk (budget / 8, TFMM_HCAP_MB)
   size_t budget = 0, used = 0;
   std::recursive_mutex mu;
@@ -193,8 +223,20 @@ struct tfmm_ctx_s {
   // wait for memory, jobs completed and jobs failed
   uint64_t n_launch = 0, n_parked = 0, n_done = 0, n_failed = 0;
   std::vector<tfmm_op> ops;
+  std::vector<tfmm_basis> bases;
+  std::vector<tfmm_near> nears;
+  // far-field matvec intermediates (A and B of the translation), grown on demand
+  void* mv_buf = nullptr;
+  size_t mv_bytes = 0;
   std::string noalloc_error;           // why the fixed scratch is unavailable (empty: available)
 };
+
+namespace tfmm {
+int near_rows(tfmm_near m) { return m ? m->n : 0; }
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+}  // namespace tfmm
+
+static void free_basis(tfmm_ctx c, tfmm_basis b);
 
 // ---------------------------------------------------------------------------
 // Budget and scratch
@@ -359,8 +401,8 @@ tfmm_status plan_zstage(tfmm_op op) {
     op->KC = KC;
     op->lds = (int)need;
   }
-  // the z-stage's pencil transform reuses the restoration's LDS
-  op->lds = (int)std::max<size_t>((size_t)op->lds, tfmm::zpencil_lds_bytes(n3, op->cb));
+  // the z-stage's y- and z-stages reuse the restoration's LDS
+  op->lds = (int)std::max<size_t>((size_t)op->lds, tfmm::zplanes_lds_bytes(n3, op->cb));
   // fused path: cubic grids whose half spectrum (n*n*zp complex64) fits in LDS
   op->fused = false;
   if (!op->ctx->no_fused && ch.fused != 0 && n1 == n2 && n2 == n3 &&
@@ -500,31 +542,23 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
   return plan_zstage(op);
 }
 
-// Scratch of one translation: the half spectrum of a chunk of ndl directions
-// (three-pass pipeline), the per-direction cores of the 4-D formats, and the
-// z-major copies of A and B for short z extents.
+// Scratch of one translation: the x-FFT'ed planes of a chunk of ndl directions
+// (three-pass pipeline) and the per-direction cores of the 4-D formats.
 struct ScratchPlan {
   int ndl = 1;
   int rhs_group = 1;
-  bool zm = false;
-  size_t hbytes = 0, a1b = 0, zbytes = 0;
-  size_t total() const { return hbytes + a1b + zbytes; }
+  size_t hbytes = 0, a1b = 0;
+  size_t total() const { return hbytes + a1b; }
 };
 
 ScratchPlan scratch_plan(const tfmm_op_s* op, int nr_total, size_t cap) {
   ScratchPlan sp;
-  const int K3 = op->K[2], nd = op->ndir;
-  const size_t per_dir_rhs = (size_t)K3 * op->nq * sizeof(float2);
+  const int nd = op->ndir;
+  // x-FFT'ed planes of one (RHS, direction): n1 x Ky x Kz complex64
+  const size_t per_dir_rhs = (size_t)op->n[0] * op->K[1] * op->K[2] * sizeof(float2);
   sp.rhs_group = std::max(1, std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH));
   sp.ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, cap / (per_dir_rhs * sp.rhs_group)));
   sp.hbytes = op->fused ? 0 : per_dir_rhs * sp.rhs_group * sp.ndl;
-  // three-pass: A and B go through z-major copies (a z-slab of a box block is
-  // then contiguous for the xy passes; in the caller's layout it is strided by
-  // K3).  Measured faster for K3 = 8 and 16 (e.g. 256x16x16: xy passes 258 ->
-  // 227 us per launch with the copies), slower for K3 = 24 and 32.
-  sp.zm = !op->fused && K3 >= 8 && K3 <= 16;
-  const long long box = (long long)op->K[0] * op->K[1] * K3;
-  sp.zbytes = sp.zm ? (size_t)box * sp.rhs_group * sp.ndl * sizeof(float2) : 0;
   sp.hbytes = (sp.hbytes + 255) / 256 * 256;
   sp.a1b = (op->a1_bytes + 255) / 256 * 256;
   return sp;
@@ -706,11 +740,9 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], K3 = op->K[2], nd = op->ndir;
   const int nr_total = (int)As.size();
   const int rhs_group = sp.rhs_group, ndl = sp.ndl;
-  const bool zm = sp.zm;
-  const long long box = (long long)op->K[0] * op->K[1] * K3;
+  const int lines = op->K[1] * K3;  // (y, z) lines of a box block
   float2* H = (float2*)scr;
   float2* a1 = (float2*)((char*)scr + sp.hbytes);
-  float2* Zs = (float2*)((char*)scr + sp.hbytes + sp.a1b);
   const bool prof0 = c->prof;
   c->prof = prof0 && prof;
   struct Restore {
@@ -777,25 +809,12 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
     for (int p0 = 0; p0 < nd; p0 += ndl) {
       const int nl = std::min(ndl, nd - p0);
       bool ok = false;
-      tfmm::RhsPtrs PZ{};
-      if (zm) {
-        for (int i = 0; i < nr; ++i) {
-          PZ.a[i] = Zs + (long long)i * nl * box;
-          PZ.b[i] = Zs + (long long)i * nl * box;
-        }
-        Launch L(c, st, "box_to_zmajor");
-        HIP_TRY(tfmm::launch_box_zmajor(true, P, Zs, op->K[0], op->K[1], K3, nr, p0, nl, op->d_perm, st));
-        L.done();
-      }
       {
-        Launch L(c, st, "fwd_xy");
-        if (zm)
-          HIP_TRY(tfmm::launch_fwd_xy(PZ, H, n1, n2, K3, nr, 0, nl, nullptr, twx, st, &ok, true));
-        else
-          HIP_TRY(tfmm::launch_fwd_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, twx, st, &ok));
+        Launch L(c, st, "fwd_x");
+        HIP_TRY(tfmm::launch_fwd_x(P, H, n1, lines, nr, p0, nl, op->d_perm, twx, st, &ok));
         L.done();
       }
-      if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "xy-FFT sizes unsupported");
+      if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "x-FFT size unsupported");
       z.p0 = p0;
       z.nrhs = nr;
       z.ndl = nl;
@@ -806,18 +825,11 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
       }
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "z-stage size unsupported");
       {
-        Launch L(c, st, "inv_xy");
-        if (zm)
-          HIP_TRY(tfmm::launch_inv_xy(PZ, H, n1, n2, K3, nr, 0, nl, nullptr, scale, twx, st, &ok, true));
-        else
-          HIP_TRY(tfmm::launch_inv_xy(P, H, n1, n2, K3, nr, p0, nl, op->d_perm, scale, twx, st, &ok));
+        Launch L(c, st, "inv_x");
+        HIP_TRY(tfmm::launch_inv_x(P, H, n1, lines, nr, p0, nl, op->d_perm, scale, twx, st, &ok));
         L.done();
       }
-      if (zm) {
-        Launch L(c, st, "zmajor_to_box");
-        HIP_TRY(tfmm::launch_box_zmajor(false, P, Zs, op->K[0], op->K[1], K3, nr, p0, nl, op->d_perm, st));
-        L.done();
-      }
+      if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "x-FFT size unsupported");
     }
   }
   return TFMM_OK;
@@ -1132,6 +1144,7 @@ const char* tfmm_status_str(tfmm_status s) {
     case TFMM_ERR_QUEUE_FULL: return "queue full";
     case TFMM_ERR_INTERNAL: return "internal error";
     case TFMM_ERR_NO_DEVICE: return "no HIP device";
+    case TFMM_ERR_NOT_CONVERGED: return "iterative solve did not converge";
   }
   return "unknown status";
 }
@@ -1156,6 +1169,8 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   c->no_fused = nf && nf[0] == '1';
   const char* nt = std::getenv("TFMM_NO_TK2");
   c->no_tk2 = nt && nt[0] == '1';
+  const char* hc4 = std::getenv("TFMM_HOST_COMPRESS");
+  c->host_compress = hc4 && hc4[0] == '1';
   // fewer, larger three-pass chunks are faster (one chunk for every direction of
   // the 24^3-box / 162-direction / 8-RHS workload: 1.91 -> 1.81 ms per step), so
   // the chunk takes an eighth of the budget, within [64 MiB, 1 GiB]
@@ -1226,6 +1241,14 @@ tfmm_status tfmm_ctx_destroy(tfmm_ctx c) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : c->event_pool) (void)hipEventDestroy(e);
+  for (tfmm_basis b : c->bases) free_basis(c, b);
+  for (tfmm_near m : c->nears) {
+    (void)hipFree(m->d_rp);
+    (void)hipFree(m->d_ci);
+    (void)hipFree(m->d_val);
+    delete m;
+  }
+  if (c->mv_buf) (void)hipFree(c->mv_buf);
   for (tfmm_op op : c->ops) free_op(c, op);
   for (auto& kv : c->roots) (void)hipFree(kv.second);
   for (auto& s : c->scratch)
@@ -1265,7 +1288,7 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* ou
   const int n[3] = {2 * P->K[0], 2 * P->K[1], 2 * P->K[2]};
   const long long N = (long long)n[0] * n[1] * n[2];
   const size_t tbytes = (size_t)N * ndir * sizeof(double2);
-  // FP64 sampling on the device (temporary buffers, not kept)
+  // FP64 sampling and FFT on the device (temporary buffers, not kept)
   double* d_khat = nullptr;
   double2* d_T = nullptr;
   HIP_TRY(hipMalloc(&d_khat, khat.size() * sizeof(double)));
@@ -1274,7 +1297,6 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* ou
     (void)hipGetLastError();
     return fail(TFMM_ERR_OOM, "no device memory for operator sampling");
   }
-  std::vector<cd> T((size_t)N * ndir);
   hipError_t e = hipMemcpy(d_khat, khat.data(), khat.size() * sizeof(double), hipMemcpyHostToDevice);
   const int near_rule = (int)P->near_rule;
   const double near_param = P->near_param > 0 ? P->near_param : (near_rule == 0 ? 1.0 : 4.0);
@@ -1282,26 +1304,52 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* ou
   if (e == hipSuccess)
     e = tfmm::launch_sample(d_T, d_khat, ndir, P->K, P->box_size, P->k_re, P->k_im, L, near_rule, near_param,
                             scale0 ? 1.0 : P->scale_re, scale0 ? 0.0 : P->scale_im, 0);
-  if (e == hipSuccess) e = hipMemcpy(T.data(), d_T, tbytes, hipMemcpyDeviceToHost);
-  (void)hipFree(d_T);
+  if (e == hipSuccess) e = hipStreamSynchronize(0);
   (void)hipFree(d_khat);
-  if (e != hipSuccess) return fail(TFMM_ERR_HIP, std::string("operator sampling: ") + hipGetErrorString(e));
-  // FP64 FFT and compression on the host
-  tfmm::fft3d_forward(T.data(), n[0], n[1], n[2], ndir);
+  if (e != hipSuccess) {
+    (void)hipFree(d_T);
+    return fail(TFMM_ERR_HIP, std::string("operator sampling: ") + hipGetErrorString(e));
+  }
+  std::string err = tfmm::fft3d_forward_device(d_T, n, ndir, 0);
+  if (!err.empty()) {
+    (void)hipFree(d_T);
+    return fail(TFMM_ERR_HIP, "operator FFT: " + err);
+  }
+  // compression (Algorithms 1-3): the 4-D formats on the device, the
+  // per-direction 3-D formats on the host
   tfmm_op op = new_op(c, P, ndir, L);
   const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::string err = tfmm::compress_operator(T, ndir, n, (int)P->fmt, P->fmt == TFMM_FMT_FULL ? 0.0 : P->tol, op->host,
-                                            nthreads);
+  const bool four_d = P->fmt == TFMM_FMT_TUCKER4D || P->fmt == TFMM_FMT_TT4D || P->fmt == TFMM_FMT_HTUCKER4D;
+  if (four_d && !c->host_compress) {
+    err = tfmm::compress_4d_device(d_T, ndir, n, (int)P->fmt, P->tol, op->host, nthreads, 0);
+    (void)hipFree(d_T);
+  } else {
+    std::vector<cd> T((size_t)N * ndir);
+    e = hipMemcpy(T.data(), d_T, tbytes, hipMemcpyDeviceToHost);
+    (void)hipFree(d_T);
+    if (e != hipSuccess) {
+      delete op;
+      return fail(TFMM_ERR_HIP, std::string("operator copy: ") + hipGetErrorString(e));
+    }
+    err = tfmm::compress_operator(T, ndir, n, (int)P->fmt, P->fmt == TFMM_FMT_FULL ? 0.0 : P->tol, op->host,
+                                  nthreads);
+  }
   if (!err.empty()) {
     delete op;
     return fail(TFMM_ERR_INTERNAL, "compression: " + err);
   }
-  T.clear();
-  T.shrink_to_fit();
   s = build_device_op(c, op);
   if (s != TFMM_OK) {
     free_op(c, op);
     return s;
+  }
+  if (!P->dirs) {
+    op->physical = true;
+    op->khat = khat;
+    op->wts = w;
+    op->k_re = P->k_re;
+    op->k_im = P->k_im;
+    op->box = P->box_size;
   }
   fill_info(op, now_s() - t0);
   c->ops.push_back(op);
@@ -1507,6 +1555,260 @@ tfmm_status tfmm_translate_noalloc(tfmm_ctx c, tfmm_op op, const void* A, void* 
     Bs[i] = (float2*)B + i * blk;
   }
   return enqueue_translate(c, op, As, Bs, st, base + tfmm::kNoAllocCounterBytes, sp, counter, false);
+}
+
+// ---------------------------------------------------------------------------
+// Far-field matvec around the translation: patterns (Eq. (3)), aggregation
+// (Eq. (4)), projection (Eq. (6))
+// ---------------------------------------------------------------------------
+
+static void free_basis(tfmm_ctx c, tfmm_basis b) {
+  dev_free(c, b->d_pat, (size_t)b->ndir * b->N * sizeof(float4));
+  dev_free(c, b->d_start, (size_t)(b->nbox + 1) * sizeof(int));
+  dev_free(c, b->d_orig, (size_t)b->N * sizeof(int));
+  dev_free(c, b->d_boxof, (size_t)b->N * sizeof(int));
+  dev_free(c, b->d_w, (size_t)b->ndir * sizeof(float));
+  delete b;
+}
+
+tfmm_status tfmm_basis_setup(tfmm_ctx c, tfmm_op op, int32_t n_basis, const double* pos, const double* orient,
+                             tfmm_basis* out) {
+  if (!c || !op || !out) return fail(TFMM_ERR_INVALID_ARG, "ctx, op or out is NULL");
+  if (op->ctx != c) return fail(TFMM_ERR_INVALID_ARG, "operator belongs to another context");
+  if (n_basis < 1 || !pos || !orient) return fail(TFMM_ERR_INVALID_ARG, "need n_basis >= 1, pos and orient");
+  if (!op->physical)
+    return fail(TFMM_ERR_UNSUPPORTED, "the operator carries no direction quadrature (imported or explicit directions)");
+  const int K1 = op->K[0], K2 = op->K[1], K3 = op->K[2];
+  const int nbox = K1 * K2 * K3, N = n_basis, nd = op->ndir;
+  // box of every basis function (grid corner at the origin), sorted by box
+  std::vector<int> box(N);
+  for (int n = 0; n < N; ++n) {
+    int v[3];
+    for (int i = 0; i < 3; ++i) {
+      const double x = pos[3 * (size_t)n + i] / op->box;
+      if (!(x >= 0.0) || !(x < (double)op->K[i])) return fail(TFMM_ERR_INVALID_ARG, "basis position outside the box grid");
+      v[i] = (int)std::floor(x);
+    }
+    const double un = orient[3 * (size_t)n] * orient[3 * (size_t)n] + orient[3 * (size_t)n + 1] * orient[3 * (size_t)n + 1] +
+                      orient[3 * (size_t)n + 2] * orient[3 * (size_t)n + 2];
+    if (!(std::fabs(un - 1.0) <= 1e-6)) return fail(TFMM_ERR_INVALID_ARG, "orientations must be unit vectors");
+    box[n] = (v[0] * K2 + v[1]) * K3 + v[2];
+  }
+  std::vector<int> order(N);
+  for (int n = 0; n < N; ++n) order[n] = n;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return box[a] < box[b]; });
+  std::vector<int> start(nbox + 1, 0), boxof(N);
+  std::vector<double> geo(6 * (size_t)N);
+  for (int i = 0; i < N; ++i) {
+    const int n = order[i], v = box[n];
+    boxof[i] = v;
+    start[v + 1] += 1;
+    const int vx = v / (K2 * K3), vy = (v / K3) % K2, vz = v % K3;
+    const double cen[3] = {(vx + 0.5) * op->box, (vy + 0.5) * op->box, (vz + 0.5) * op->box};
+    for (int d = 0; d < 3; ++d) {
+      geo[6 * (size_t)i + d] = pos[3 * (size_t)n + d] - cen[d];
+      geo[6 * (size_t)i + 3 + d] = orient[3 * (size_t)n + d];
+    }
+  }
+  for (int v = 0; v < nbox; ++v) start[v + 1] += start[v];
+  std::vector<float> wf(nd);
+  for (int p = 0; p < nd; ++p) wf[p] = (float)op->wts[p];
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  tfmm_basis b = new tfmm_basis_s();
+  b->ctx = c;
+  b->op = op;
+  b->N = N;
+  b->nbox = nbox;
+  b->ndir = nd;
+  tfmm_status s = dev_alloc(c, (void**)&b->d_pat, (size_t)nd * N * sizeof(float4));
+  if (s == TFMM_OK) s = dev_alloc(c, (void**)&b->d_start, (size_t)(nbox + 1) * sizeof(int));
+  if (s == TFMM_OK) s = dev_alloc(c, (void**)&b->d_orig, (size_t)N * sizeof(int));
+  if (s == TFMM_OK) s = dev_alloc(c, (void**)&b->d_boxof, (size_t)N * sizeof(int));
+  if (s == TFMM_OK) s = dev_alloc(c, (void**)&b->d_w, (size_t)nd * sizeof(float));
+  if (s != TFMM_OK) {
+    free_basis(c, b);
+    return s;
+  }
+  b->bytes = (size_t)nd * N * sizeof(float4) + (size_t)(nbox + 1 + 2 * N) * sizeof(int) + nd * sizeof(float);
+  double *d_khat = nullptr, *d_geo = nullptr;
+  hipError_t e = hipMalloc(&d_khat, op->khat.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&d_geo, geo.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMemcpy(d_khat, op->khat.data(), op->khat.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_start, start.data(), start.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_orig, order.data(), N * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_boxof, boxof.data(), N * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_w, wf.data(), nd * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = tfmm::launch_dipole_patterns(b->d_pat, d_khat, d_geo, N, nd, op->k_re, op->k_im, 0);
+  if (e == hipSuccess) e = hipStreamSynchronize(0);
+  if (d_khat) (void)hipFree(d_khat);
+  if (d_geo) (void)hipFree(d_geo);
+  if (e != hipSuccess) {
+    free_basis(c, b);
+    return fail(TFMM_ERR_HIP, std::string("basis patterns: ") + hipGetErrorString(e));
+  }
+  op->refs.fetch_add(1);
+  c->bases.push_back(b);
+  *out = b;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_basis_release(tfmm_ctx c, tfmm_basis b) {
+  if (!c || !b) return fail(TFMM_ERR_INVALID_ARG, "ctx or basis is NULL");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  auto it = std::find(c->bases.begin(), c->bases.end(), b);
+  if (it == c->bases.end()) return fail(TFMM_ERR_INVALID_ARG, "basis does not belong to this context");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->bases.erase(it);
+  b->op->refs.fetch_sub(1);
+  free_basis(c, b);
+  return TFMM_OK;
+}
+
+static tfmm_status check_basis(tfmm_ctx c, tfmm_basis b, const void* x, const void* y, int32_t nrhs) {
+  if (!c || !b) return fail(TFMM_ERR_INVALID_ARG, "ctx or basis is NULL");
+  if (b->ctx != c) return fail(TFMM_ERR_INVALID_ARG, "basis belongs to another context");
+  if (!x || !y) return fail(TFMM_ERR_INVALID_ARG, "input or output is NULL");
+  if (nrhs < 1 || nrhs > 4096) return fail(TFMM_ERR_INVALID_ARG, "nrhs out of range");
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_aggregate(tfmm_ctx c, tfmm_basis b, const void* I, void* A, int32_t nrhs, void* stream) {
+  tfmm_status s = check_basis(c, b, I, A, nrhs);
+  if (s != TFMM_OK) return s;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  Launch L(c, (hipStream_t)stream, "aggregate");
+  HIP_TRY(tfmm::launch_aggregate(b->d_pat, b->d_start, b->d_orig, (const float2*)I, (float2*)A, b->N, b->nbox, b->ndir,
+                                 nrhs, (hipStream_t)stream));
+  L.done();
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_disaggregate(tfmm_ctx c, tfmm_basis b, const void* B, void* y, int32_t nrhs, void* stream) {
+  tfmm_status s = check_basis(c, b, B, y, nrhs);
+  if (s != TFMM_OK) return s;
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  Launch L(c, (hipStream_t)stream, "disaggregate");
+  HIP_TRY(tfmm::launch_disaggregate(b->d_pat, b->d_boxof, b->d_orig, b->d_w, (const float2*)B, (float2*)y, b->N,
+                                    b->nbox, b->ndir, nrhs, (hipStream_t)stream));
+  L.done();
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_farfield_matvec(tfmm_ctx c, tfmm_op op, tfmm_basis b, const void* I, void* y, int32_t nrhs,
+                                 void* stream) {
+  tfmm_status s = check_basis(c, b, I, y, nrhs);
+  if (s != TFMM_OK) return s;
+  if (!op || op != b->op) return fail(TFMM_ERR_INVALID_ARG, "op must be the operator the basis was set up with");
+  if (2 * nrhs > 4096) return fail(TFMM_ERR_INVALID_ARG, "nrhs out of range");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  hipStream_t st = (hipStream_t)stream;
+  // A and B of the translation: 2 nrhs fields (theta, phi) per direction and box
+  const size_t half = (size_t)2 * nrhs * op->ndir * b->nbox * sizeof(float2);
+  const size_t need = (2 * half + 255) / 256 * 256;
+  if (c->mv_bytes < need) {
+    if (c->mv_buf) {
+      (void)hipDeviceSynchronize();
+      dev_free(c, c->mv_buf, c->mv_bytes);
+      c->mv_buf = nullptr;
+      c->mv_bytes = 0;
+    }
+    s = dev_alloc(c, &c->mv_buf, need);
+    if (s != TFMM_OK) return s;
+    c->mv_bytes = need;
+  }
+  float2* A = (float2*)c->mv_buf;
+  float2* B = (float2*)((char*)c->mv_buf + half);
+  {
+    Launch L(c, st, "aggregate");
+    HIP_TRY(tfmm::launch_aggregate(b->d_pat, b->d_start, b->d_orig, (const float2*)I, A, b->N, b->nbox, b->ndir,
+                                   nrhs, st));
+    L.done();
+  }
+  s = tfmm_translate(c, op, A, B, 2 * nrhs, stream);
+  if (s != TFMM_OK) return s;
+  Launch L(c, st, "disaggregate");
+  HIP_TRY(tfmm::launch_disaggregate(b->d_pat, b->d_boxof, b->d_orig, b->d_w, B, (float2*)y, b->N, b->nbox, b->ndir,
+                                    nrhs, st));
+  L.done();
+  return TFMM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Near-field matrix (caller-supplied CSR) and the TFQMR solve (solver.cpp)
+// ---------------------------------------------------------------------------
+
+static void free_near(tfmm_ctx c, tfmm_near m) {
+  dev_free(c, m->d_rp, (size_t)(m->n + 1) * sizeof(int));
+  dev_free(c, m->d_ci, (size_t)m->nnz * sizeof(int));
+  dev_free(c, m->d_val, (size_t)m->nnz * sizeof(float2));
+  delete m;
+}
+
+tfmm_status tfmm_near_setup(tfmm_ctx c, int32_t n, const int32_t* row_ptr, const int32_t* cols, const double* vals,
+                            tfmm_near* out) {
+  if (!c || !out || !row_ptr) return fail(TFMM_ERR_INVALID_ARG, "ctx, out or row_ptr is NULL");
+  if (n < 1) return fail(TFMM_ERR_INVALID_ARG, "n must be >= 1");
+  if (row_ptr[0] != 0) return fail(TFMM_ERR_INVALID_ARG, "row_ptr[0] must be 0");
+  for (int i = 0; i < n; ++i)
+    if (row_ptr[i + 1] < row_ptr[i]) return fail(TFMM_ERR_INVALID_ARG, "row_ptr must be non-decreasing");
+  const long long nnz = row_ptr[n];
+  if (nnz > 0 && (!cols || !vals)) return fail(TFMM_ERR_INVALID_ARG, "cols or vals is NULL");
+  for (long long j = 0; j < nnz; ++j)
+    if (cols[j] < 0 || cols[j] >= n) return fail(TFMM_ERR_INVALID_ARG, "column index out of range");
+  std::vector<float2> v((size_t)nnz);
+  for (long long j = 0; j < nnz; ++j) v[j] = make_float2((float)vals[2 * j], (float)vals[2 * j + 1]);
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  tfmm_near m = new tfmm_near_s();
+  m->ctx = c;
+  m->n = n;
+  m->nnz = std::max(1LL, nnz);
+  tfmm_status s = dev_alloc(c, (void**)&m->d_rp, (size_t)(n + 1) * sizeof(int));
+  if (s == TFMM_OK) s = dev_alloc(c, (void**)&m->d_ci, (size_t)std::max(1LL, nnz) * sizeof(int));
+  if (s == TFMM_OK) s = dev_alloc(c, (void**)&m->d_val, (size_t)std::max(1LL, nnz) * sizeof(float2));
+  if (s != TFMM_OK) {
+    free_near(c, m);
+    return s;
+  }
+  hipError_t e = hipMemcpy(m->d_rp, row_ptr, (size_t)(n + 1) * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->d_ci, cols, (size_t)nnz * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess && nnz > 0) e = hipMemcpy(m->d_val, v.data(), (size_t)nnz * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_near(c, m);
+    return fail(TFMM_ERR_HIP, std::string("near-field upload: ") + hipGetErrorString(e));
+  }
+  c->nears.push_back(m);
+  *out = m;
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_near_release(tfmm_ctx c, tfmm_near m) {
+  if (!c || !m) return fail(TFMM_ERR_INVALID_ARG, "ctx or near is NULL");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  auto it = std::find(c->nears.begin(), c->nears.end(), m);
+  if (it == c->nears.end()) return fail(TFMM_ERR_INVALID_ARG, "near-field matrix does not belong to this context");
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->nears.erase(it);
+  free_near(c, m);
+  return TFMM_OK;
+}
+
+tfmm_status tfmm_near_matvec(tfmm_ctx c, tfmm_near m, const void* x, void* y, int32_t nrhs, void* stream) {
+  if (!c || !m || !x || !y) return fail(TFMM_ERR_INVALID_ARG, "ctx, near, x or y is NULL");
+  if (m->ctx != c) return fail(TFMM_ERR_INVALID_ARG, "near-field matrix belongs to another context");
+  if (nrhs < 1) return fail(TFMM_ERR_INVALID_ARG, "nrhs must be >= 1");
+  std::lock_guard<std::recursive_mutex> g(c->mu);
+  HIP_TRY(hipSetDevice(c->device));
+  HIP_TRY(tfmm::launch_near_spmv(m->d_rp, m->d_ci, m->d_val, (const float2*)x, (float2*)y, m->n, nrhs,
+                                 (hipStream_t)stream));
+  return TFMM_OK;
 }
 
 tfmm_status tfmm_submit(tfmm_ctx c, tfmm_op op, const void* A, void* B, int32_t nrhs, tfmm_ticket* out) {

@@ -471,6 +471,36 @@ long long factor_elems(int fmt, const int n[3], int ndir, const std::vector<int3
   return -1;
 }
 
+// Interior nodes of the balanced H-Tucker tree {1,2}{3,4} (Algorithm 2, steps
+// 5-10) from the leaf core C (r1 x r2 x r3 x r4) and the leaf bases; fills the
+// import layout U1..U4, C12, C34, root.
+void htucker_interior(const std::vector<cd>& C, const int r[4], const std::vector<std::vector<cd>>& leaves,
+                      double budget2, double nx2, Factors& out, int nthreads) {
+  const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3];
+  int m12 = r1 * r2, m34 = r3 * r4;
+  // W12 = core as (r1 r2) x (r3 r4); C12 from W12, C34 from W12^T (Algorithm 2 steps 5-8)
+  Basis c12 = left_basis(C, m12, m34, budget2, nthreads);
+  std::vector<cd> Wt((size_t)m34 * m12);
+  for (int i = 0; i < m12; ++i)
+    for (int j = 0; j < m34; ++j) Wt[(size_t)j * m12 + i] = C[(size_t)i * m34 + j];
+  Basis c34 = left_basis(Wt, m34, m12, budget2, nthreads);
+  // root B = C12^H W12 conj(C34)  (steps 9-10): first T = C12^H W12 (r12 x m34)
+  std::vector<cd> T = adjoint_times(c12.U, m12, c12.r, C, m34, nthreads);
+  std::vector<cd> Bm((size_t)c12.r * c34.r, 0.0);
+  for (int i = 0; i < c12.r; ++i)
+    for (int j = 0; j < c34.r; ++j) {
+      cd s = 0.0;
+      for (int k = 0; k < m34; ++k) s += T[(size_t)i * m34 + k] * std::conj(c34.U[(size_t)k * c34.r + j]);
+      Bm[(size_t)i * c34.r + j] = s;
+    }
+  out.ranks = {r1, r2, r3, r4, c12.r, c34.r};
+  out.rel_err = std::sqrt(std::max(0.0, nx2 - norm2(Bm)) / nx2);
+  for (int m = 0; m < 4; ++m) append(out.data, leaves[m]);
+  append(out.data, c12.U);  // C12[a1][a2][b]
+  append(out.data, c34.U);  // C34[a3][a4][b']
+  append(out.data, Bm);
+}
+
 std::string compress_operator(const std::vector<cd>& That, int ndir, const int n[3], int fmt, double gamma,
                               Factors& out, int nthreads) {
   const long long N = (long long)n[0] * n[1] * n[2];
@@ -556,29 +586,10 @@ std::string compress_operator(const std::vector<cd>& That, int ndir, const int n
       for (int m = 0; m < 4; ++m) append(out.data, B[m].U);
       return "";
     }
-    int r1 = B[0].r, r2 = B[1].r, r3 = B[2].r, r4 = B[3].r;
-    int m12 = r1 * r2, m34 = r3 * r4;
-    // W12 = core as (r1 r2) x (r3 r4); C12 from W12, C34 from W12^T (Algorithm 2 steps 5-8)
-    Basis c12 = left_basis(C, m12, m34, budget2, nthreads);
-    std::vector<cd> Wt((size_t)m34 * m12);
-    for (int i = 0; i < m12; ++i)
-      for (int j = 0; j < m34; ++j) Wt[(size_t)j * m12 + i] = C[(size_t)i * m34 + j];
-    Basis c34 = left_basis(Wt, m34, m12, budget2, nthreads);
-    // root B = C12^H W12 conj(C34)  (steps 9-10): first T = C12^H W12 (r12 x m34)
-    std::vector<cd> T = adjoint_times(c12.U, m12, c12.r, C, m34, nthreads);
-    std::vector<cd> Bm((size_t)c12.r * c34.r, 0.0);
-    for (int i = 0; i < c12.r; ++i)
-      for (int j = 0; j < c34.r; ++j) {
-        cd s = 0.0;
-        for (int k = 0; k < m34; ++k) s += T[(size_t)i * m34 + k] * std::conj(c34.U[(size_t)k * c34.r + j]);
-        Bm[(size_t)i * c34.r + j] = s;
-      }
-    out.ranks = {r1, r2, r3, r4, c12.r, c34.r};
-    out.rel_err = std::sqrt(std::max(0.0, nx2 - norm2(Bm)) / nx2);
-    for (int m = 0; m < 4; ++m) append(out.data, B[m].U);
-    append(out.data, c12.U);  // C12[a1][a2][b]
-    append(out.data, c34.U);  // C34[a3][a4][b']
-    append(out.data, Bm);
+    std::vector<std::vector<cd>> leaves(4);
+    for (int m = 0; m < 4; ++m) leaves[m] = B[m].U;
+    const int r[4] = {B[0].r, B[1].r, B[2].r, B[3].r};
+    htucker_interior(C, r, leaves, budget2, nx2, out, nthreads);
     return "";
   }
   if (fmt == 4) {

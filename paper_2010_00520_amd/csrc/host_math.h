@@ -57,6 +57,14 @@ struct Factors {
 std::string compress_operator(const std::vector<cd>& That, int ndir, const int n[3], int fmt,
                               double gamma, Factors& out, int nthreads);
 
+// Interior nodes of the balanced H-Tucker tree {1,2}{3,4} (Algorithm 2, steps
+// 5-10) from the leaf core C (r1 x r2 x r3 x r4, C order) and the leaf bases
+// U_m (n_m x r_m, row-major): truncation with the tail budget budget2 (squared),
+// relative error from nx2 = ||X||_F^2.  Writes ranks, rel_err and the import
+// layout U1..U4, C12, C34, root into `out`.
+void htucker_interior(const std::vector<cd>& C, const int r[4], const std::vector<std::vector<cd>>& leaves,
+                      double budget2, double nx2, Factors& out, int nthreads);
+
 // Number of complex entries the import layout holds for a format and ranks;
 // -1 if the ranks are inconsistent.
 long long factor_elems(int fmt, const int n[3], int ndir, const std::vector<int32_t>& ranks);

@@ -1,10 +1,10 @@
 // Translation kernels for gfx950: Eq. (5) with operators restored on the fly.
 //
-//   pass 1  k_fwd_xy   zero-padded x- and y-FFTs of A per (rhs, direction, z-slab), in LDS
-//   pass 2  k_zstage   per (direction, pencil tile): restore the operator tile on the
-//                      matrix cores (Figs. 3-4), then z-FFT, multiply, inverse z-FFT of
-//                      every RHS directly in the accumulator lane layout
-//   pass 3  k_inv_xy   inverse y- and x-FFTs, crop to the box grid, scale 1/N
+//   pass 1  k_fwd_x    zero-padded x-FFT of A (xpass.hip)
+//   pass 2  k_zstage   per (direction, tile of whole fx planes): restore the operator
+//                      tile on the matrix cores (Figs. 3-4), then for every RHS the
+//                      y-FFT, z-FFT, product, inverse z- and y-FFTs in LDS (stages.h)
+//   pass 3  k_inv_x    inverse x-FFT, crop to the box grid, scale 1/N (xpass.hip)
 //   a1      k_cgemm    batched complex GEMMs producing per-direction cores of the
 //                      4-D formats (Fig. 3(b)(c), Fig. 4(b) step 1)
 //   setup   k_sample   FP64 operator samples, Eq. (7)
@@ -126,173 +126,6 @@ __global__ void k_pack_full(const float2* __restrict__ src, float4* __restrict__
 hipError_t launch_pack_full(const float2* src, float4* dst, int ndir, int nq, int n3, hipStream_t st) {
   dim3 grid((nq + 255) / 256, n3 / 2, ndir);
   hipLaunchKernelGGL(k_pack_full, grid, dim3(256), 0, st, src, dst, nq, n3);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Pass 1 / pass 3 of the three-pass pipeline: xy-FFTs of a slab of zg
-// z-planes per (rhs, direction); the half spectrum goes through device memory
-// as H[rhs][dir][z][q] (pencil index q = fx*n2 + fy fastest).
-// ---------------------------------------------------------------------------
-template <int N1, int N2>
-__global__ __launch_bounds__(TFMM_BLOCK) void k_fwd_xy(RhsPtrs P, float2* __restrict__ H, int K3, int zg, int zp,
-                                                       int ndl, int p0, const int* __restrict__ perm,
-                                                       const float2* __restrict__ twx, bool zm) {
-  extern __shared__ float2 lds[];
-  constexpr int K1 = N1 / 2, K2 = N2 / 2, NQ = N1 * N2;
-  const int s = blockIdx.z, pl = blockIdx.y, z0 = blockIdx.x * zg;
-  const int p = perm ? perm[p0 + pl] : p0 + pl;
-  const float2* __restrict__ Ab = P.a[s] + (long long)p * ((long long)K1 * K2 * K3);
-  xy_forward<N1, N2, TFMM_BLOCK>(lds, Ab, K3, zg, zp, z0, twx, zm);
-  __syncthreads();
-  float2* Hb = H + ((long long)s * ndl + pl) * ((long long)K3 * NQ) + (long long)z0 * NQ;
-  for (int e = threadIdx.x; e < zg * NQ; e += TFMM_BLOCK) {
-    const int z = e / NQ, q = e - z * NQ;
-    Hb[e] = lds[q * zp + z];
-  }
-}
-
-template <int N1, int N2>
-__global__ __launch_bounds__(TFMM_BLOCK) void k_inv_xy(RhsPtrs P, const float2* __restrict__ H, int K3, int zg,
-                                                       int zp, int ndl, int p0, const int* __restrict__ perm,
-                                                       float scale, const float2* __restrict__ twx, bool zm) {
-  extern __shared__ float2 lds[];
-  constexpr int K1 = N1 / 2, K2 = N2 / 2, NQ = N1 * N2;
-  const int s = blockIdx.z, pl = blockIdx.y, z0 = blockIdx.x * zg;
-  const float2* Hb = H + ((long long)s * ndl + pl) * ((long long)K3 * NQ) + (long long)z0 * NQ;
-  for (int e = threadIdx.x; e < zg * NQ; e += TFMM_BLOCK) {
-    const int z = e / NQ, q = e - z * NQ;
-    lds[q * zp + z] = Hb[e];
-  }
-  __syncthreads();
-  const int p = perm ? perm[p0 + pl] : p0 + pl;
-  float2* __restrict__ Bb = P.b[s] + (long long)p * ((long long)K1 * K2 * K3);
-  xy_inverse<N1, N2, TFMM_BLOCK>(lds, Bb, K3, zg, zp, z0, scale, twx, zm);
-}
-
-static void xy_slab(int n1, int n2, int K3, int* zg, int* zp) {
-  // largest divisor of K3 whose padded slab fits 64 KB of LDS
-  int best = 1;
-  for (int d = 1; d <= K3; ++d) {
-    if (K3 % d) continue;
-    int p = (d & 1) ? d : d + 1;
-    if ((size_t)n1 * n2 * p * sizeof(float2) <= 65536) best = d;
-  }
-  *zg = best;
-  *zp = (best & 1) ? best : best + 1;
-}
-
-#define TFMM_XY_SIZES(X) X(8) X(16) X(24) X(32) X(48) X(64)
-#define TFMM_X_SIZES(X) X(8) X(16) X(24) X(32) X(48) X(64) X(128) X(256)
-
-template <int N1>
-static bool dispatch_fwd_n2(int n2, const RhsPtrs& P, float2* H, int K3, int nrhs, int p0, int ndl,
-                            const int* perm, const float2* twx, bool zm, hipStream_t st) {
-  int zg, zp;
-  switch (n2) {
-#define CASE2(N2)                                                                                      \
-  case N2: {                                                                                           \
-    xy_slab(N1, N2, K3, &zg, &zp);                                                                     \
-    size_t lds = (size_t)N1 * N2 * zp * sizeof(float2);                                                \
-    hipLaunchKernelGGL((k_fwd_xy<N1, N2>), dim3(K3 / zg, ndl, nrhs), dim3(TFMM_BLOCK), lds, st, P, H, K3, \
-                       zg, zp, ndl, p0, perm, twx, zm);                                                \
-    return true;                                                                                       \
-  }
-    TFMM_XY_SIZES(CASE2)
-#undef CASE2
-  }
-  return false;
-}
-
-template <int N1>
-static bool dispatch_inv_n2(int n2, const RhsPtrs& P, const float2* H, int K3, int nrhs, int p0, int ndl,
-                            const int* perm, float scale, const float2* twx, bool zm, hipStream_t st) {
-  int zg, zp;
-  switch (n2) {
-#define CASE2(N2)                                                                                      \
-  case N2: {                                                                                           \
-    xy_slab(N1, N2, K3, &zg, &zp);                                                                     \
-    size_t lds = (size_t)N1 * N2 * zp * sizeof(float2);                                                \
-    hipLaunchKernelGGL((k_inv_xy<N1, N2>), dim3(K3 / zg, ndl, nrhs), dim3(TFMM_BLOCK), lds, st, P, H, K3, \
-                       zg, zp, ndl, p0, perm, scale, twx, zm);                                         \
-    return true;                                                                                       \
-  }
-    TFMM_XY_SIZES(CASE2)
-#undef CASE2
-  }
-  return false;
-}
-
-hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const int* perm, const float2* twx, hipStream_t st, bool* supported, bool zm) {
-  bool ok = false;
-  switch (n1) {
-#define CASE1(N1) \
-  case N1: ok = dispatch_fwd_n2<N1>(n2, P, H, K3, nrhs, p0, ndl, perm, twx, zm, st); break;
-    TFMM_X_SIZES(CASE1)
-#undef CASE1
-  }
-  *supported = ok;
-  return ok ? hipGetLastError() : hipSuccess;
-}
-
-hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported, bool zm) {
-  bool ok = false;
-  switch (n1) {
-#define CASE1(N1) \
-  case N1: ok = dispatch_inv_n2<N1>(n2, P, H, K3, nrhs, p0, ndl, perm, scale, twx, zm, st); break;
-    TFMM_X_SIZES(CASE1)
-#undef CASE1
-  }
-  *supported = ok;
-  return ok ? hipGetLastError() : hipSuccess;
-}
-
-// ---------------------------------------------------------------------------
-// z-major staging of the box blocks for the three-pass pipeline.  Block b of
-// RHS s and launch-local direction d (global direction perm[p0 + d]) is a
-// (K1 K2) x K3 matrix in the caller's layout; its staged copy at
-// Z + (s ndl + d) K1 K2 K3 is the transpose (K3 x K1 K2), so the xy passes read
-// and write whole z-planes.  Tiles of 64 rows go through LDS (odd row stride).
-// ---------------------------------------------------------------------------
-template <bool TO_Z>
-__global__ __launch_bounds__(256) void k_box_zmajor(RhsPtrs P, float2* __restrict__ Z, int R, int K3, int ndl, int p0,
-                                                    const int* __restrict__ perm) {
-  __shared__ float2 t[64 * 65];
-  const int s = blockIdx.z, d = blockIdx.y, r0 = blockIdx.x * 64, S = K3 + 1;
-  const int p = perm ? perm[p0 + d] : p0 + d;
-  const long long blk = (long long)R * K3;
-  float2* zb = Z + ((long long)s * ndl + d) * blk;
-  const int nr = min(64, R - r0);
-  if (TO_Z) {
-    const float2* src = P.a[s] + (long long)p * blk;
-    for (int e = threadIdx.x; e < nr * K3; e += 256) t[(e / K3) * S + e % K3] = src[(long long)r0 * K3 + e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * K3; e += 256) {
-      const int z = e >> 6, rl = e & 63;
-      if (rl < nr) zb[(long long)z * R + r0 + rl] = t[rl * S + z];
-    }
-  } else {
-    float2* dst = P.b[s] + (long long)p * blk;
-    for (int e = threadIdx.x; e < 64 * K3; e += 256) {
-      const int z = e >> 6, rl = e & 63;
-      if (rl < nr) t[rl * S + z] = zb[(long long)z * R + r0 + rl];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nr * K3; e += 256) dst[(long long)r0 * K3 + e] = t[(e / K3) * S + e % K3];
-  }
-}
-
-hipError_t launch_box_zmajor(bool to_z, const RhsPtrs& P, float2* Z, int K1, int K2, int K3, int nrhs, int p0,
-                             int ndl, const int* perm, hipStream_t st) {
-  if (K3 > 64) return hipErrorInvalidValue;
-  const int R = K1 * K2;
-  const dim3 grid((unsigned)((R + 63) / 64), (unsigned)ndl, (unsigned)nrhs);
-  if (to_z)
-    hipLaunchKernelGGL((k_box_zmajor<true>), grid, dim3(256), 0, st, P, Z, R, K3, ndl, p0, perm);
-  else
-    hipLaunchKernelGGL((k_box_zmajor<false>), grid, dim3(256), 0, st, P, Z, R, K3, ndl, p0, perm);
   return hipGetLastError();
 }
 

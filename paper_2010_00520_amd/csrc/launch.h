@@ -16,7 +16,7 @@ struct ZArgs {
   int fmt;
   int n1, n2, n3, K3, nq;
   int p0, nrhs, ndl;          // first direction, RHS count, directions in this launch
-  float2* H;                  // [nrhs][ndl][K3][nq]
+  float2* H;                  // x-FFT'ed planes G [nrhs][ndl][n1][n2/2][K3]
   const float4* Tfull;        // FULL: [n_dir][n3/2][nq] (consecutive fz pairs)
   const float2* cbase;        // cores (op data or scratch)
   const float2* fbase;        // factors (op data)
@@ -44,9 +44,13 @@ struct ZArgs {
 // LDS bytes a restoration of a qt-pencil tile needs for a format / ranks /
 // chunk (host-side planning; qt = n1*n2 for the fused kernel).
 size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1, int r2);
-// LDS of the three-pass z-stage's pencil transform: four waves, 16 cb pencils
-// each, rows of n3 + 1 complex.
-inline size_t zpencil_lds_bytes(int n3, int cb) { return (size_t)4 * 16 * cb * (n3 + 1) * 8; }
+// LDS of the three-pass z-stage's y- and z-stages (zstage_planes): the
+// restored tile (64 cb pencils, rows of n3 + 1 complex), the tile's half
+// spectrum (rows of K3 | 1) and its x-FFT'ed planes (32 cb rows of K3 | 1).
+inline size_t zplanes_lds_bytes(int n3, int cb) {
+  const size_t qt = (size_t)64 * cb, kp = (size_t)((n3 / 2) | 1);
+  return (qt * (n3 + 1) + qt * kp + qt / 2 * kp) * 8;
+}
 // LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf);
 
@@ -58,20 +62,15 @@ struct RhsPtrs {
   float2* b[TFMM_MAX_RHS_PER_LAUNCH];
 };
 
-// xy passes of the three-pass pipeline.  n1 in {8,...,64, 128, 256}, n2 <= 64;
-// twx = exp(-2 pi i m / n1), m < n1, is read only when n1 > 64.
-// Direction p0 + d of the launch is perm[p0 + d] (perm NULL: p0 + d).
-// zm: A (forward) / B (inverse) are z-major staged copies (see launch_box_zmajor).
-hipError_t launch_fwd_xy(const RhsPtrs& P, float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const int* perm, const float2* twx, hipStream_t st, bool* supported, bool zm = false);
-hipError_t launch_inv_xy(const RhsPtrs& P, const float2* H, int n1, int n2, int K3, int nrhs, int p0, int ndl,
-                         const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported,
-                         bool zm = false);
-// Box blocks of the launch (RHS s < nrhs, directions perm[p0 + d], d < ndl) to
-// (to_z: from P.a) or from (P.b) their z-major copies at Z + (s*ndl + d)*K1*K2*K3,
-// element (x, y, z) at (z*K1 + x)*K2 + y.  K3 <= 64.
-hipError_t launch_box_zmajor(bool to_z, const RhsPtrs& P, float2* Z, int K1, int K2, int K3, int nrhs, int p0,
-                             int ndl, const int* perm, hipStream_t st);
+// x passes of the three-pass pipeline (xpass.hip): G[s][d][fx][y][z] (y, z
+// over the box grid; `lines` = Ky Kz) from A, and back to B with the crop and
+// scale.  n1 in {8, ..., 64, 128, 256}; twx = exp(-2 pi i m / n1), m < n1, is
+// read only when n1 > 64.  Direction p0 + d of the launch is perm[p0 + d]
+// (perm NULL: p0 + d).
+hipError_t launch_fwd_x(const RhsPtrs& P, float2* G, int n1, int lines, int nrhs, int p0, int ndl, const int* perm,
+                        const float2* twx, hipStream_t st, bool* supported);
+hipError_t launch_inv_x(const RhsPtrs& P, const float2* G, int n1, int lines, int nrhs, int p0, int ndl,
+                        const int* perm, float scale, const float2* twx, hipStream_t st, bool* supported);
 // Zero n ints (a kernel, so that it may be captured in a graph).
 hipError_t launch_zero(int* p, int n, hipStream_t st);
 hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported);
@@ -101,6 +100,29 @@ hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, lo
 hipError_t launch_sample(double2* T, const double* khat, int ndir, const int K[3], double box, double kre,
                          double kim, int L, int near_rule, double near_param, double scale_re, double scale_im,
                          hipStream_t st);
+
+// Setup permutations of complex128 tensors (setup_kernels.hip):
+// out[c][r] = in[r][c] for a rows x cols matrix (rows <= 2^21);
+hipError_t launch_transpose64(const double2* in, double2* out, long long rows, long long cols, hipStream_t st);
+// [P][D][Q] -> [D][P][Q] (to_first) or back.
+hipError_t launch_perm_mode(const double2* in, double2* out, long long P, long long D, long long Q, bool to_first,
+                            hipStream_t st);
+
+// Far-field matvec around the translation (farfield.hip): point-dipole
+// patterns pat[p][n] = (theta.u, phi.u, Re e, Im e) from geo[n] = (r_n - r_v, u_n)
+// in FP64 (Eq. (3)); aggregation A[2r+c][p][v] (Eq. (4)); projection
+// y[r][orig(n)] (Eq. (6)); the near-field CSR product; precision conversions.
+hipError_t launch_dipole_patterns(float4* pat, const double* khat, const double* geo, int N, int ndir, double kre,
+                                  double kim, hipStream_t st);
+hipError_t launch_aggregate(const float4* pat, const int* start, const int* orig, const float2* I, float2* A, int N,
+                            int nbox, int ndir, int nrhs, hipStream_t st);
+hipError_t launch_disaggregate(const float4* pat, const int* boxof, const int* orig, const float* w, const float2* B,
+                               float2* y, int N, int nbox, int ndir, int nrhs, hipStream_t st);
+hipError_t launch_near_spmv(const int* rp, const int* ci, const float2* val, const float2* x, float2* y, int n,
+                            int nrhs, hipStream_t st);
+hipError_t launch_narrow128(const double2* a, float2* b, int n, hipStream_t st);
+hipError_t launch_widen(const float2* a, double2* b, int n, hipStream_t st);
+hipError_t launch_sum_widen(const float2* a, const float2* c, double2* b, int n, hipStream_t st);
 
 // Pack complex64 FULL operator [p][n1 n2 n3] into the [p][n3/2][nq] float4 layout.
 hipError_t launch_pack_full(const float2* src, float4* dst, int ndir, int nq, int n3, hipStream_t st);

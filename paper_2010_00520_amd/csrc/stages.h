@@ -443,24 +443,67 @@ __device__ __forceinline__ void zfft_pencils32(const float2 (&tz)[NP][32], float
 }
 
 // ---------------------------------------------------------------------------
-// z-stage of the three-pass pipeline with whole pencils per lane.  The
-// restored tile (wave w: 16 CB pencils, lane (g, j) of column block c holding
-// fz = 8t + 2g + {0,1} of pencil 16c + j) is written once to an LDS region of
-// the wave, one row of N3 frequencies per pencil (odd row stride); lane l then
-// owns pencil l of the wave.  Per RHS a lane reads its K3 = N3/2 nonzero
-// inputs (coalesced over lanes: consecutive pencils are consecutive in H),
-// splits the pruned N3-point transform into even and odd outputs,
-//   X[2m] = DFT_K3(x)[m],  X[2m+1] = DFT_K3(x[z] w^z)[m],
-//   y[z'] = IDFT_K3(P_even)[z'] + w^-z' IDFT_K3(P_odd)[z'],   z' < K3,
-// (w = exp(-2 pi i / N3), P = X * T~), and writes its K3 outputs back.
+// y- and z-stages of the three-pass pipeline on the tile's x-FFT'ed planes.
+// A tile of QT = 64 CB pencils (q = fx n2 + fy) covers nf = QT / n2 whole fx
+// planes.  The restored tile (wave w: 16 CB pencils, lane (g, j) of column
+// block c holding fz = 8t + 2g + {0,1} of pencil 16c + j) is written once to an
+// LDS region, one row of N3 frequencies per pencil (odd row stride); lane l of
+// wave w then owns tile pencil w 16 CB + l.  Per RHS the block
+//   1. loads the nf planes G[fx][y][z] (y < n2/2, z < K3 = N3/2; one
+//      contiguous run) into LDS,
+//   2. runs the zero-padded y-FFTs of every (fx, z) line into the tile's half
+//      spectrum, one row of K3 per pencil,
+//   3. per pencil (one lane each) splits the pruned N3-point z transform into
+//      even and odd outputs, X[2m] = DFT_K3(x)[m], X[2m+1] = DFT_K3(x[z] w^z)[m],
+//      multiplies by T~ and inverts: y[z'] = IDFT_K3(P_even)[z'] + w^-z'
+//      IDFT_K3(P_odd)[z'], z' < K3 (w = exp(-2 pi i / N3)),
+//   4. runs the inverse y-FFTs of every (fx, z) line, keeping y < n2/2,
+//   5. stores the planes back in place.
 // ---------------------------------------------------------------------------
+template <int N2>
+__device__ __forceinline__ void yline_fwd(const float2* src, int ss, float2* dst, int ds) {
+  float2 x[N2 / 2], X[N2];
+#pragma unroll
+  for (int i = 0; i < N2 / 2; ++i) x[i] = src[i * ss];
+  Dft<N2>::fwd(x, X);
+#pragma unroll
+  for (int f = 0; f < N2; ++f) dst[f * ds] = X[f];
+}
+
+template <int N2>
+__device__ __forceinline__ void yline_inv(const float2* src, int ss, float2* dst, int ds) {
+  float2 x[N2], X[N2 / 2];
+#pragma unroll
+  for (int f = 0; f < N2; ++f) x[f] = src[f * ss];
+  Dft<N2>::inv(x, X);
+#pragma unroll
+  for (int i = 0; i < N2 / 2; ++i) dst[i * ds] = X[i];
+}
+
+// y lines of length n2 = 64 CB / nf (a divisor of the tile width)
+template <int CB>
+__device__ __forceinline__ void yline(bool fwd, int n2, const float2* src, int ss, float2* dst, int ds) {
+#define TFMM_YL(N)                                                    \
+  case N:                                                             \
+    if constexpr ((64 * CB) % N == 0) {                               \
+      if (fwd) yline_fwd<N>(src, ss, dst, ds);                        \
+      else yline_inv<N>(src, ss, dst, ds);                            \
+    }                                                                 \
+    break;
+  switch (n2) { TFMM_YL(8) TFMM_YL(16) TFMM_YL(24) TFMM_YL(32) TFMM_YL(48) TFMM_YL(64) }
+#undef TFMM_YL
+}
+
 template <int T, int CB>
-__device__ __forceinline__ void zstage_pencils(const v4f (&acc)[T][CB], const ZArgs& a, int pl, int q0,
-                                               float2* lds) {
-  constexpr int N3 = 8 * T, K = 4 * T, PS = N3 + 1, NPW = 16 * CB;
-  static_assert(NPW <= 64, "one pencil per lane");  // LDS: zpencil_lds_bytes
+__device__ __forceinline__ void zstage_planes(const v4f (&acc)[T][CB], const ZArgs& a, int pl, int q0,
+                                              float2* lds) {
+  constexpr int N3 = 8 * T, K = 4 * T, PS = N3 + 1, NPW = 16 * CB, QT = 4 * NPW, KP = K | 1;
+  static_assert(NPW <= 64, "one pencil per lane");  // LDS: zplanes_lds_bytes
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, j = l & 15;
+  const int n2 = a.n2, K2 = n2 / 2, nf = QT / n2, fx0 = q0 / n2;
   float2* reg = lds + w * (NPW * PS);
+  float2* Hl = lds + QT * PS;     // [QT][KP]: tile half spectrum
+  float2* Y = Hl + QT * KP;       // [nf K2][KP]: planes, y < K2
   __syncthreads();  // the restoration is done with its LDS
 #pragma unroll
   for (int c = 0; c < CB; ++c)
@@ -469,17 +512,25 @@ __device__ __forceinline__ void zstage_pencils(const v4f (&acc)[T][CB], const ZA
 #pragma unroll
       for (int e = 0; e < 2; ++e)
         reg[(c * 16 + j) * PS + 8 * t + 2 * g + e] = make_float2(acc[t][c][2 * e], acc[t][c][2 * e + 1]);
-  __syncthreads();
-  const int q = q0 + w * NPW + l;
-  if (l < NPW && q < a.nq) {
-    const float2* tz = reg + l * PS;
-    const float2* wz = a.roots;  // wz[z] = w^z
-    const long long zs = a.nq;
-    for (int s = 0; s < a.nrhs; ++s) {
-      float2* h = a.H + ((long long)s * a.ndl + pl) * ((long long)a.K3 * a.nq) + q;
+  const int nel = nf * K2 * K;    // complex entries of the tile's planes
+  const int nline = nf * K;       // (fx, z) lines
+  const float2* tz = reg + l * PS;
+  const float2* wz = a.roots;     // wz[z] = w^z
+  for (int s = 0; s < a.nrhs; ++s) {
+    float2* gp = a.H + (((long long)s * a.ndl + pl) * a.n1 + fx0) * ((long long)K2 * K);
+    __syncthreads();  // previous RHS done with Y (and the tile is in place)
+    for (int e = threadIdx.x; e < nel; e += TFMM_BLOCK) Y[(e / K) * KP + e % K] = gp[e];
+    __syncthreads();
+    for (int task = threadIdx.x; task < nline; task += TFMM_BLOCK) {
+      const int f = task / K, z = task - f * K;
+      yline<CB>(true, n2, Y + f * K2 * KP + z, KP, Hl + f * n2 * KP + z, KP);
+    }
+    __syncthreads();
+    if (l < NPW) {
+      float2* h = Hl + (w * NPW + l) * KP;
       float2 x[K], E[K], ye[K];
 #pragma unroll
-      for (int z = 0; z < K; ++z) x[z] = h[z * zs];
+      for (int z = 0; z < K; ++z) x[z] = h[z];
       DftFull<K>::fwd(x, E);
 #pragma unroll
       for (int z = 0; z < K; ++z) x[z] = cmul(x[z], wz[z]);
@@ -491,8 +542,15 @@ __device__ __forceinline__ void zstage_pencils(const v4f (&acc)[T][CB], const ZA
       for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m + 1]);
       DftFull<K>::inv(E, x);
 #pragma unroll
-      for (int z = 0; z < K; ++z) h[z * zs] = cadd(ye[z], cmulconj(x[z], wz[z]));
+      for (int z = 0; z < K; ++z) h[z] = cadd(ye[z], cmulconj(x[z], wz[z]));
     }
+    __syncthreads();
+    for (int task = threadIdx.x; task < nline; task += TFMM_BLOCK) {
+      const int f = task / K, z = task - f * K;
+      yline<CB>(false, n2, Hl + f * n2 * KP + z, KP, Y + f * K2 * KP + z, KP);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nel; e += TFMM_BLOCK) gp[e] = Y[(e / K) * KP + e % K];
   }
   __syncthreads();  // the region is reused by the next item's restoration
 }
@@ -537,7 +595,7 @@ __device__ __forceinline__ void zstage_item(const ZArgs& a, int it, float2* lds)
   const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
   v4f acc[T][CB];
   restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
-  zstage_pencils<T, CB>(acc, a, pl, q0, lds);
+  zstage_planes<T, CB>(acc, a, pl, q0, lds);
 }
 
 // The first item of every block is its own index; only a launch with more

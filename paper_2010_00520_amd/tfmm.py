@@ -23,7 +23,7 @@ NEAR = {"cheb": 0, "kappa": 1}
 STATUS = {
     0: "ok", 1: "invalid argument", 2: "unsupported", 3: "device-memory budget exhausted",
     4: "out of memory", 5: "HIP error", 6: "operator busy", 7: "unknown ticket", 8: "queue full",
-    9: "internal error", 10: "no HIP device",
+    9: "internal error", 10: "no HIP device", 11: "iterative solve did not converge",
 }
 
 
@@ -114,6 +114,18 @@ SIGNATURES = [
                             ctypes.POINTER(ctypes.c_double)]),
     ("tfmm_op_plan", _ST, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.c_size_t]),
     ("tfmm_sched_stats", _ST, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t]),
+    ("tfmm_basis_setup", _ST, [_VP, _VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_VP)]),
+    ("tfmm_basis_release", _ST, [_VP, _VP]),
+    ("tfmm_aggregate", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    ("tfmm_disaggregate", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    ("tfmm_farfield_matvec", _ST, [_VP, _VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    ("tfmm_near_setup", _ST, [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_VP)]),
+    ("tfmm_near_release", _ST, [_VP, _VP]),
+    ("tfmm_near_matvec", _ST, [_VP, _VP, _VP, _VP, ctypes.c_int32, _VP]),
+    ("tfmm_solve_tfqmr", _ST, [_VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int32,
+                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)]),
 ]
 
 _lib = None
@@ -235,6 +247,36 @@ class Operator:
             self.handle = ctypes.c_void_p(0)
 
 
+class Basis:
+    """Point-dipole basis functions of the far-field product (tfmm_basis_setup)."""
+
+    def __init__(self, ctx: "Context", op: "Operator", handle: int, n: int):
+        self.ctx, self.op, self.handle, self.n = ctx, op, ctypes.c_void_p(handle), n
+
+    def release(self):
+        if self.handle:
+            _check(load().tfmm_basis_release(self.ctx.handle, self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+
+class NearField:
+    """Near-field matrix of the system (CSR, tfmm_near_setup)."""
+
+    def __init__(self, ctx: "Context", handle: int, n: int):
+        self.ctx, self.handle, self.n = ctx, ctypes.c_void_p(handle), n
+
+    def release(self):
+        if self.handle:
+            _check(load().tfmm_near_release(self.ctx.handle, self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+
+def _check_vec(t, shape, name):
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _dev_ptr(t)
+
+
 class Context:
     """One GPU, one device-memory budget, one scheduler."""
 
@@ -335,6 +377,71 @@ class Context:
         v = (ctypes.c_uint64 * 5)()
         _check(load().tfmm_sched_stats(self.handle, v, 5))
         return dict(zip(("launches", "memory_waits", "done", "failed", "queued"), (int(x) for x in v)))
+
+    def basis(self, op: Operator, pos, orient) -> Basis:
+        """Point dipoles at pos (n, 3) with unit orientations orient (n, 3)."""
+        p = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+        u = np.ascontiguousarray(np.asarray(orient, dtype=np.float64).reshape(-1, 3))
+        if p.shape != u.shape:
+            raise ValueError("pos and orient must have the same shape")
+        h = ctypes.c_void_p()
+        _check(load().tfmm_basis_setup(self.handle, op.handle, p.shape[0],
+                                       p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                       u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
+        return Basis(self, op, h.value, p.shape[0])
+
+    def aggregate(self, basis: Basis, I, A, stream=None):
+        """Eq. (4): I [nrhs, n_basis] -> A [2 nrhs, n_dir, Kx, Ky, Kz]."""
+        nrhs = int(I.shape[0])
+        a = _check_vec(A, (2 * nrhs,) + basis.op.block, "A")
+        _check(load().tfmm_aggregate(self.handle, basis.handle, ctypes.c_void_p(_check_vec(I, (nrhs, basis.n), "I")),
+                                     ctypes.c_void_p(a), nrhs, ctypes.c_void_p(_stream_handle(stream))))
+
+    def disaggregate(self, basis: Basis, B, y, stream=None):
+        """Eq. (6): B [2 nrhs, n_dir, Kx, Ky, Kz] -> y [nrhs, n_basis]."""
+        nrhs = int(y.shape[0])
+        b = _check_vec(B, (2 * nrhs,) + basis.op.block, "B")
+        _check(load().tfmm_disaggregate(self.handle, basis.handle, ctypes.c_void_p(b),
+                                        ctypes.c_void_p(_check_vec(y, (nrhs, basis.n), "y")), nrhs,
+                                        ctypes.c_void_p(_stream_handle(stream))))
+
+    def farfield_matvec(self, op: Operator, basis: Basis, I, y, stream=None):
+        """Far-field product y = Zfar I (aggregate, translate, project)."""
+        nrhs = int(I.shape[0])
+        _check(load().tfmm_farfield_matvec(self.handle, op.handle, basis.handle,
+                                           ctypes.c_void_p(_check_vec(I, (nrhs, basis.n), "I")),
+                                           ctypes.c_void_p(_check_vec(y, (nrhs, basis.n), "y")), nrhs,
+                                           ctypes.c_void_p(_stream_handle(stream))))
+
+    def near(self, n, row_ptr, cols, vals) -> NearField:
+        """Near-field matrix from host CSR arrays (vals complex)."""
+        rp = np.ascontiguousarray(np.asarray(row_ptr, dtype=np.int32))
+        ci = np.ascontiguousarray(np.asarray(cols, dtype=np.int32))
+        v = np.ascontiguousarray(np.asarray(vals, dtype=np.complex128)).view(np.float64)
+        h = ctypes.c_void_p()
+        _check(load().tfmm_near_setup(self.handle, int(n), rp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      ci.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h)))
+        return NearField(self, h.value, int(n))
+
+    def near_matvec(self, near: NearField, x, y, stream=None):
+        nrhs = int(x.shape[0])
+        _check(load().tfmm_near_matvec(self.handle, near.handle, ctypes.c_void_p(_check_vec(x, (nrhs, near.n), "x")),
+                                       ctypes.c_void_p(_check_vec(y, (nrhs, near.n), "y")), nrhs,
+                                       ctypes.c_void_p(_stream_handle(stream))))
+
+    def solve_tfqmr(self, op: Operator, basis: Basis, near: NearField, V, I, tol=1e-6, maxit=500):
+        """Solve (Zn + Zfar) I = V; returns (iterations, relative residual).  Waits
+        for torch's current stream first (the solve runs on its own stream)."""
+        import torch
+
+        v = _check_vec(V, (basis.n,), "V")
+        i = _check_vec(I, (basis.n,), "I")
+        torch.cuda.current_stream().synchronize()
+        it, rr = ctypes.c_int32(), ctypes.c_double()
+        _check(load().tfmm_solve_tfqmr(self.handle, op.handle, basis.handle, near.handle, ctypes.c_void_p(v),
+                                       ctypes.c_void_p(i), float(tol), int(maxit), ctypes.byref(it), ctypes.byref(rr)))
+        return it.value, rr.value
 
     def set_profiling(self, on: bool):
         _check(load().tfmm_set_profiling(self.handle, 1 if on else 0))

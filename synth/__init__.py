@@ -155,3 +155,24 @@ def sphere_dipoles(K, box: float, n: int, seed: int, radius_frac: float = 0.45):
 def current_vector(n: int, nrhs: int, seed: int) -> np.ndarray:
     """Basis-function coefficients I (nrhs, n), complex64 Gaussian."""
     return gaussian_patterns((nrhs, n), seed)
+
+
+def near_field_csr(box_of: np.ndarray, K, seed: int, diag: complex, offdiag: float):
+    """A synthetic near-field matrix in CSR form for basis functions with box
+    coordinates box_of (n, 3): for every pair (m, n) whose boxes are within one
+    box of each other (max |v_m - v_n| <= 1), a seeded complex Gaussian entry of
+    scale `offdiag`; `diag` on the diagonal.  Returns (row_ptr, cols, vals)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    v = np.asarray(box_of)
+    n = v.shape[0]
+    rows, cols, vals = [0], [], []
+    for m in range(n):
+        near = np.nonzero(np.max(np.abs(v - v[m]), axis=1) <= 1)[0]
+        for j in near:
+            cols.append(int(j))
+            if j == m:
+                vals.append(complex(diag))
+            else:
+                vals.append(offdiag * complex(rng.standard_normal(), rng.standard_normal()))
+        rows.append(len(cols))
+    return np.array(rows, np.int32), np.array(cols, np.int32), np.array(vals, np.complex128)

@@ -32,8 +32,10 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 # Relative L2 bound of the GPU arithmetic (FP32 FFTs and products; restoration in
-# FP32 or split-bf16 with FP32 accumulation) against FP64 on the same factors.
-ARITH_TOL = {"fp32": 2e-5, "bf16x3": 1e-4}
+# FP32 or split-bf16 with FP32 accumulation) against FP64 on the same factors:
+# about four times the largest error measured over these cases (FP32 5.2e-7,
+# bf16x3 9.5e-6), so an arithmetic slip well below the compression error fails.
+ARITH_TOL = {"fp32": 2e-6, "bf16x3": 3e-5}
 
 CASES = [
     # (workload, format, gamma)
