@@ -88,7 +88,7 @@ struct tfmm_op_s {
   std::vector<int> desc;               // host copy of the descriptors
   // derived plan: three-pass pipeline (cb, KC, lds) and, for small cubic
   // grids, the fused single-kernel path (fused, fKC, flds)
-  int zfmt = 0, cb = 1, KC = 8, lds = 0;
+  int zfmt = 0, cb = 1, KC = 8, lds = 0, rg = 1;
   bool fused = false;
   int fKC = 8, flds = 0;
   // Tucker family: register-chained restoration (3-pass tile / fused tile)
@@ -401,8 +401,15 @@ tfmm_status plan_zstage(tfmm_op op) {
     op->KC = KC;
     op->lds = (int)need;
   }
-  // the z-stage's y- and z-stages reuse the restoration's LDS
-  op->lds = (int)std::max<size_t>((size_t)op->lds, tfmm::zplanes_lds_bytes(n3, op->cb));
+  // the z-stage's y- and z-stages reuse the restoration's LDS; RHS go through in
+  // groups of rg half spectra, as many as fit
+  op->rg = 1;
+  for (int rg : {4, 2})
+    if (tfmm::zplanes_lds_bytes(n3, op->cb, rg) <= lds_max) {
+      op->rg = rg;
+      break;
+    }
+  op->lds = (int)std::max<size_t>((size_t)op->lds, tfmm::zplanes_lds_bytes(n3, op->cb, op->rg));
   // fused path: cubic grids whose half spectrum (n*n*zp complex64) fits in LDS
   op->fused = false;
   if (!op->ctx->no_fused && ch.fused != 0 && n1 == n2 && n2 == n3 &&
@@ -773,6 +780,7 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
   z.lds_bytes = op->lds;
   z.bf = op->prec == TFMM_PREC_BF16X3 ? 1 : 0;
   z.tk2 = op->tk2 ? 1 : 0;
+  z.rg = op->rg;
   z.perm = op->d_perm;
   z.counter = counter;
   z.ncu = c->ncu;

@@ -29,6 +29,7 @@ struct ZArgs {
   int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
   int bf;                     // 1: split-BF16 (bf16x3) restoration, 0: FP32
   int tk2;                    // Tucker: 1 = register-chained restoration (tucker_restore.h)
+  int rg;                     // three-pass z-stage: RHS per group (half spectra held in LDS)
   // persistent launch: work items are taken from counter[0], counter[1]
   // counts finished blocks (both zero between launches; the last block
   // resets them); direction order perm[] (costliest first, NULL = identity)
@@ -45,11 +46,11 @@ struct ZArgs {
 // chunk (host-side planning; qt = n1*n2 for the fused kernel).
 size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1, int r2);
 // LDS of the three-pass z-stage's y- and z-stages (zstage_planes): the
-// restored tile (64 cb pencils, rows of n3 + 1 complex), the tile's half
-// spectrum (rows of K3 | 1) and its x-FFT'ed planes (32 cb rows of K3 | 1).
-inline size_t zplanes_lds_bytes(int n3, int cb) {
+// restored tile (64 cb pencils, rows of n3 + 1 complex) and the tile's half
+// spectra of rg RHS at a time (rows of K3 | 1).
+inline size_t zplanes_lds_bytes(int n3, int cb, int rg) {
   const size_t qt = (size_t)64 * cb, kp = (size_t)((n3 / 2) | 1);
-  return (qt * (n3 + 1) + qt * kp + qt / 2 * kp) * 8;
+  return (qt * (n3 + 1) + (size_t)rg * qt * kp) * 8;
 }
 // LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf);

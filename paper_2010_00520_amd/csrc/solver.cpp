@@ -164,7 +164,8 @@ extern "C" tfmm_status tfmm_solve_tfqmr(tfmm_ctx ctx, tfmm_op op, tfmm_basis bas
         tau = tau * theta * cc;
         eta = cc * cc * alpha;
         S.axpy(eta, d.p, x.p);
-        if (tau * std::sqrt((double)m + 2.0) <= tol * nb) {
+        res = tau * std::sqrt((double)m + 2.0) / nb;  // Freund's bound until a true residual is taken
+        if (res <= tol) {
           // true residual of the complex128 iterate through the operator
           S.apply(x.p, t.p);
           S.copy(b.p, r.p);

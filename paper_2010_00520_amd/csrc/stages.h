@@ -449,16 +449,18 @@ __device__ __forceinline__ void zfft_pencils32(const float2 (&tz)[NP][32], float
 // block c holding fz = 8t + 2g + {0,1} of pencil 16c + j) is written once to an
 // LDS region, one row of N3 frequencies per pencil (odd row stride); lane l of
 // wave w then owns tile pencil w 16 CB + l.  Per RHS the block
-//   1. loads the nf planes G[fx][y][z] (y < n2/2, z < K3 = N3/2; one
-//      contiguous run) into LDS,
-//   2. runs the zero-padded y-FFTs of every (fx, z) line into the tile's half
-//      spectrum, one row of K3 per pencil,
+//   1. runs the zero-padded y-FFTs of every (fx, z) line of its planes
+//      G[fx][y][z] (y < n2/2, z < K3 = N3/2), read straight from device memory
+//      (consecutive threads take consecutive z), into the tile's half spectrum
+//      in LDS, one row of K3 per pencil,
 //   3. per pencil (one lane each) splits the pruned N3-point z transform into
 //      even and odd outputs, X[2m] = DFT_K3(x)[m], X[2m+1] = DFT_K3(x[z] w^z)[m],
 //      multiplies by T~ and inverts: y[z'] = IDFT_K3(P_even)[z'] + w^-z'
 //      IDFT_K3(P_odd)[z'], z' < K3 (w = exp(-2 pi i / N3)),
-//   4. runs the inverse y-FFTs of every (fx, z) line, keeping y < n2/2,
-//   5. stores the planes back in place.
+//   4. runs the inverse y-FFTs of every (fx, z) line, keeping y < n2/2, and
+//      writes the planes back in place.
+// The RHS go through in groups of rg (a.rg, as many half spectra as LDS holds)
+// so that each phase has rg times the independent lines and pencils.
 // ---------------------------------------------------------------------------
 template <int N2>
 __device__ __forceinline__ void yline_fwd(const float2* src, int ss, float2* dst, int ds) {
@@ -500,10 +502,9 @@ __device__ __forceinline__ void zstage_planes(const v4f (&acc)[T][CB], const ZAr
   constexpr int N3 = 8 * T, K = 4 * T, PS = N3 + 1, NPW = 16 * CB, QT = 4 * NPW, KP = K | 1;
   static_assert(NPW <= 64, "one pencil per lane");  // LDS: zplanes_lds_bytes
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, j = l & 15;
-  const int n2 = a.n2, K2 = n2 / 2, nf = QT / n2, fx0 = q0 / n2;
+  const int n2 = a.n2, K2 = n2 / 2, nf = QT / n2, fx0 = q0 / n2, rg = a.rg;
   float2* reg = lds + w * (NPW * PS);
-  float2* Hl = lds + QT * PS;     // [QT][KP]: tile half spectrum
-  float2* Y = Hl + QT * KP;       // [nf K2][KP]: planes, y < K2
+  float2* Hl = lds + QT * PS;     // [rg][QT][KP]: half spectra of rg RHS
   __syncthreads();  // the restoration is done with its LDS
 #pragma unroll
   for (int c = 0; c < CB; ++c)
@@ -512,45 +513,47 @@ __device__ __forceinline__ void zstage_planes(const v4f (&acc)[T][CB], const ZAr
 #pragma unroll
       for (int e = 0; e < 2; ++e)
         reg[(c * 16 + j) * PS + 8 * t + 2 * g + e] = make_float2(acc[t][c][2 * e], acc[t][c][2 * e + 1]);
-  const int nel = nf * K2 * K;    // complex entries of the tile's planes
-  const int nline = nf * K;       // (fx, z) lines
+  const int nline = nf * K;       // (fx, z) lines per RHS
+  const long long plane = (long long)K2 * K;
   const float2* tz = reg + l * PS;
   const float2* wz = a.roots;     // wz[z] = w^z
-  for (int s = 0; s < a.nrhs; ++s) {
-    float2* gp = a.H + (((long long)s * a.ndl + pl) * a.n1 + fx0) * ((long long)K2 * K);
-    __syncthreads();  // previous RHS done with Y (and the tile is in place)
-    for (int e = threadIdx.x; e < nel; e += TFMM_BLOCK) Y[(e / K) * KP + e % K] = gp[e];
-    __syncthreads();
-    for (int task = threadIdx.x; task < nline; task += TFMM_BLOCK) {
-      const int f = task / K, z = task - f * K;
-      yline<CB>(true, n2, Y + f * K2 * KP + z, KP, Hl + f * n2 * KP + z, KP);
+  for (int s0 = 0; s0 < a.nrhs; s0 += rg) {
+    const int nr = min(rg, a.nrhs - s0);
+    __syncthreads();  // the previous group is done with the half spectra (and the tile is in place)
+    // forward y lines, read straight from the planes (consecutive threads: consecutive z)
+    for (int task = threadIdx.x; task < nr * nline; task += TFMM_BLOCK) {
+      const int r = task / nline, t2 = task - r * nline, f = t2 / K, z = t2 - f * K;
+      const float2* gp = a.H + (((long long)(s0 + r) * a.ndl + pl) * a.n1 + fx0) * plane;
+      yline<CB>(true, n2, gp + f * K2 * K + z, K, Hl + (r * QT + f * n2) * KP + z, KP);
     }
     __syncthreads();
     if (l < NPW) {
-      float2* h = Hl + (w * NPW + l) * KP;
-      float2 x[K], E[K], ye[K];
+      for (int r = 0; r < nr; ++r) {
+        float2* h = Hl + (r * QT + w * NPW + l) * KP;
+        float2 x[K], E[K], ye[K];
 #pragma unroll
-      for (int z = 0; z < K; ++z) x[z] = h[z];
-      DftFull<K>::fwd(x, E);
+        for (int z = 0; z < K; ++z) x[z] = h[z];
+        DftFull<K>::fwd(x, E);
 #pragma unroll
-      for (int z = 0; z < K; ++z) x[z] = cmul(x[z], wz[z]);
+        for (int z = 0; z < K; ++z) x[z] = cmul(x[z], wz[z]);
 #pragma unroll
-      for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m]);
-      DftFull<K>::inv(E, ye);
-      DftFull<K>::fwd(x, E);
+        for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m]);
+        DftFull<K>::inv(E, ye);
+        DftFull<K>::fwd(x, E);
 #pragma unroll
-      for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m + 1]);
-      DftFull<K>::inv(E, x);
+        for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m + 1]);
+        DftFull<K>::inv(E, x);
 #pragma unroll
-      for (int z = 0; z < K; ++z) h[z] = cadd(ye[z], cmulconj(x[z], wz[z]));
+        for (int z = 0; z < K; ++z) h[z] = cadd(ye[z], cmulconj(x[z], wz[z]));
+      }
     }
     __syncthreads();
-    for (int task = threadIdx.x; task < nline; task += TFMM_BLOCK) {
-      const int f = task / K, z = task - f * K;
-      yline<CB>(false, n2, Hl + f * n2 * KP + z, KP, Y + f * K2 * KP + z, KP);
+    // inverse y lines with the crop, written straight back to the planes
+    for (int task = threadIdx.x; task < nr * nline; task += TFMM_BLOCK) {
+      const int r = task / nline, t2 = task - r * nline, f = t2 / K, z = t2 - f * K;
+      float2* gp = a.H + (((long long)(s0 + r) * a.ndl + pl) * a.n1 + fx0) * plane;
+      yline<CB>(false, n2, Hl + (r * QT + f * n2) * KP + z, KP, gp + f * K2 * K + z, K);
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nel; e += TFMM_BLOCK) gp[e] = Y[(e / K) * KP + e % K];
   }
   __syncthreads();  // the region is reused by the next item's restoration
 }
