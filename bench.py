@@ -107,12 +107,18 @@ def fft_flops(K, n, ndir, nrhs):
     return nrhs * ndir * x, nrhs * ndir * yz
 
 
-def kernel_work(name, fmt, prec, ranks, info, K, n, ndir, nrhs):
+def kernel_work(name, fmt, prec, ranks, info, K, n, ndir, nrhs, w1=False):
     """Algorithmic work of one launch of a library kernel: (MFMA flops, VALU flops,
     HBM bytes).  Bytes count only what the method must move (the stored operator,
     A read once, B written once); the x-FFT'ed planes the three-pass pipeline
-    keeps between its passes are not algorithmic."""
+    keeps between its passes are not algorithmic.  With `w1` (4-D formats on the
+    three-pass path) the x-mode product n1 r1 r2 r3 per direction runs in its own
+    batched GEMM (`a1_w1`) instead of the z-stage."""
     a1, a2 = restore_macs(fmt, ranks, n, ndir)
+    xmode = ndir * n[0] * ranks[0] * ranks[1] * ranks[2] if w1 else 0
+    if name == "a1_w1":
+        return 8.0 * xmode, 0.0, 0
+    a2 -= xmode
     x, yz = fft_flops(K, n, ndir, nrhs)
     io = 8 * ndir * nrhs * K[0] * K[1] * K[2]
     stored = info["bytes_stored"]
@@ -594,7 +600,8 @@ def summarize(w, key, r, full, steps):
     kernels = {}
     for name, k in kt.items():
         per_step = k["launches"] / max(steps, 10)
-        work = kernel_work(name, fmt, prec, r["ranks"], info, w.K, w.n, w.n_dir, w.nrhs)
+        work = kernel_work(name, fmt, prec, r["ranks"], info, w.K, w.n, w.n_dir, w.nrhs,
+                           w1=r.get("plan", {}).get("w1_formed", False))
         kernels[name] = {"avg_ms": k["avg_ms"], "launches_per_step": per_step,
                          **({"roofline": roofline_of(name, k["avg_ms"], work, prec)} if any(work) else {})}
     dom = max(kt, key=lambda n: kt[n]["avg_ms"] * kt[n]["launches"])

@@ -377,7 +377,10 @@ tfmm_status tfmm_autotune(tfmm_ctx ctx, tfmm_op op, int32_t nrhs, int32_t reps, 
                           double* best_ms);
 
 /* The operator's current plan: {fused 0/1, three-pass cb, register-chained
- * restoration 0/1, 1 if chosen by the autotuner}; writes min(cap, 4) values. */
+ * restoration 0/1, 1 if chosen by the autotuner, 1 if the x-mode product of the
+ * per-direction cores (Fig. 3(a) step 1) is formed by a batched GEMM ahead of
+ * the z-stage (Tucker-4D / H-Tucker-4D on the three-pass path)}; writes
+ * min(cap, 5) values. */
 tfmm_status tfmm_op_plan(tfmm_op op, int32_t* out, size_t cap);
 
 /* ---- diagnostics ------------------------------------------------------------ */

@@ -25,7 +25,8 @@ NO_PK = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 # host code calling the HIP runtime and ROCm libraries (operator setup, solver)
 HOST_HIP_UNITS = ("setup_gpu", "solver")
-DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tt3d", "zstage_tt4d", "noalloc", "setup_kernels", "xpass", "farfield")
+DEVICE_UNITS = ("kernels", "zstage_full", "zstage_tucker", "zstage_tuckerw", "zstage_tt3d", "zstage_tt4d", "noalloc",
+                "setup_kernels", "xpass", "farfield")
 
 
 def _run(cmd):

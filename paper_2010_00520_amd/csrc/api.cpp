@@ -93,6 +93,10 @@ struct tfmm_op_s {
   int fKC = 8, flds = 0;
   // Tucker family: register-chained restoration (3-pass tile / fused tile)
   bool tk2 = false, ftk2 = false;
+  // 4-D formats on the three-pass path: the x-mode product W1[fx][b][c] of each
+  // direction's core is formed by a batched GEMM per direction chunk, and the
+  // z-stage restores from it (ZF_TUCKER_W1)
+  bool use_w1 = false;
   size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
   int* d_perm = nullptr;               // direction order, costliest restoration first (NULL: identity)
   float2* d_roots_z = nullptr;         // exp(-2 pi i m / n3), m < n3 (context table)
@@ -167,6 +171,7 @@ struct tfmm_ctx_s {
   int device = 0;
   bool no_fused = false;               // TFMM_NO_FUSED=1: always use the three-pass pipeline
   bool no_tk2 = false;                 // TFMM_NO_TK2=1: Tucker restoration through LDS-staged products
+  bool no_w1 = false;                  // TFMM_NO_W1=1: 4-D formats restore the x-mode product in the z-stage
   bool host_compress = false;          // TFMM_HOST_COMPRESS=1: compress the 4-D formats on the host
   size_t hcap = (size_t)256 << 20;     // three-pass half-spectrum chunk (budget / 8, TFMM_HCAP_MB)
   size_t budget = 0, used = 0;
@@ -437,6 +442,15 @@ tfmm_status plan_zstage(tfmm_op op) {
       op->flds = (int)std::max(hbytes, rb);
     }
   }
+  op->use_w1 = false;
+  if ((op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D) && !op->fused && op->tk2 &&
+      !op->ctx->no_w1) {
+    const size_t need_w1 = tfmm::tucker2_lds_bytes(n2, n3, 64 * op->cb, r1, r2, bf, true);
+    if (need_w1 <= lds_max) {
+      op->use_w1 = true;
+      op->lds = (int)std::max<size_t>((size_t)op->lds, need_w1);
+    }
+  }
   return TFMM_OK;
 }
 
@@ -554,20 +568,28 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
 struct ScratchPlan {
   int ndl = 1;
   int rhs_group = 1;
-  size_t hbytes = 0, a1b = 0;
-  size_t total() const { return hbytes + a1b; }
+  size_t hbytes = 0, a1b = 0, w1b = 0;  // planes, per-call cores, x-mode products of a direction chunk
+  size_t total() const { return hbytes + a1b + w1b; }
 };
+
+// x-mode product W1[fx][c][b] of one direction (4-D formats: uniform ranks)
+size_t w1_elems_per_dir(const tfmm_op_s* op) {
+  const auto& r = op->host.ranks;
+  return (size_t)op->n[0] * r[1] * r[2];
+}
 
 ScratchPlan scratch_plan(const tfmm_op_s* op, int nr_total, size_t cap) {
   ScratchPlan sp;
   const int nd = op->ndir;
   // x-FFT'ed planes of one (RHS, direction): n1 x Ky x Kz complex64
   const size_t per_dir_rhs = (size_t)op->n[0] * op->K[1] * op->K[2] * sizeof(float2);
+  const size_t w1_dir = op->use_w1 ? w1_elems_per_dir(op) * sizeof(float2) : 0;
   sp.rhs_group = std::max(1, std::min(nr_total, TFMM_MAX_RHS_PER_LAUNCH));
-  sp.ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, cap / (per_dir_rhs * sp.rhs_group)));
+  sp.ndl = (int)std::max<size_t>(1, std::min<size_t>((size_t)nd, cap / (per_dir_rhs * sp.rhs_group + w1_dir)));
   sp.hbytes = op->fused ? 0 : per_dir_rhs * sp.rhs_group * sp.ndl;
   sp.hbytes = (sp.hbytes + 255) / 256 * 256;
   sp.a1b = (op->a1_bytes + 255) / 256 * 256;
+  sp.w1b = (w1_dir * sp.ndl + 255) / 256 * 256;
   return sp;
 }
 
@@ -750,6 +772,7 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
   const int lines = op->K[1] * K3;  // (y, z) lines of a box block
   float2* H = (float2*)scr;
   float2* a1 = (float2*)((char*)scr + sp.hbytes);
+  float2* W1 = (float2*)((char*)scr + sp.hbytes + sp.a1b);
   const bool prof0 = c->prof;
   c->prof = prof0 && prof;
   struct Restore {
@@ -764,13 +787,17 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
   float2* roots = op->d_roots_z;
   float2* twx = op->d_roots_x;
   tfmm::ZArgs z{};
-  z.fmt = op->zfmt;
+  z.fmt = op->use_w1 && !op->fused ? tfmm::ZF_TUCKER_W1 : op->zfmt;
   z.n1 = n1; z.n2 = n2; z.n3 = n3; z.K3 = K3; z.nq = op->nq;
   z.H = H;
   z.Tfull = op->d_full;
   z.fbase = op->d_data;
   const bool four_d = op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D;
   z.cbase = four_d ? a1 : op->d_data;
+  if (z.fmt == tfmm::ZF_TUCKER_W1) {
+    z.cbase = W1;
+    z.w1dir = (long long)w1_elems_per_dir(op);
+  }
   z.wbase = a1;
   z.vbase = a1 + (op->fmt == TFMM_FMT_TT4D ? (size_t)op->nq * op->host.ranks[1] : 0);
   z.desc = op->d_desc;
@@ -823,6 +850,18 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
         L.done();
       }
       if (!ok) return fail(TFMM_ERR_UNSUPPORTED, "x-FFT size unsupported");
+      if (z.fmt == tfmm::ZF_TUCKER_W1) {
+        // W1[p][fx][b][c] = sum_a U1[fx][a] C_p[a][b][c] for the chunk's directions
+        // (Fig. 3(a) step 1, the x-mode product, ahead of the z-stage); C_p is the
+        // per-direction core a1 formed, [p][a][b][c]
+        const auto& r = op->host.ranks;
+        const int r1 = r[0], r2 = r[1], r3 = r[2];
+        const long long m = (long long)r1 * r2 * r3, r23 = (long long)r2 * r3;
+        Launch L(c, st, "a1_w1");
+        HIP_TRY(tfmm::launch_cgemm(n1, (int)r23, r1, nl, tfmm::GOp{op->d_data + op->desc[1], r1, 1, 0},
+                                   tfmm::GOp{a1 + (size_t)p0 * m, r23, 1, m}, W1, r23, 1, z.w1dir, st));
+        L.done();
+      }
       z.p0 = p0;
       z.nrhs = nr;
       z.ndl = nl;
@@ -1177,6 +1216,8 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
   c->no_fused = nf && nf[0] == '1';
   const char* nt = std::getenv("TFMM_NO_TK2");
   c->no_tk2 = nt && nt[0] == '1';
+  const char* nw1 = std::getenv("TFMM_NO_W1");
+  c->no_w1 = nw1 && nw1[0] == '1';
   const char* hc4 = std::getenv("TFMM_HOST_COMPRESS");
   c->host_compress = hc4 && hc4[0] == '1';
   // fewer, larger three-pass chunks are faster (one chunk for every direction of
@@ -1935,8 +1976,9 @@ tfmm_status tfmm_kernel_times(tfmm_ctx c, char* names, size_t names_cap, double*
 
 tfmm_status tfmm_op_plan(tfmm_op op, int32_t* out, size_t cap) {
   if (!op || !out) return fail(TFMM_ERR_INVALID_ARG, "op or out is NULL");
-  const int32_t v[4] = {op->fused ? 1 : 0, op->cb, (op->fused ? op->ftk2 : op->tk2) ? 1 : 0, op->tuned ? 1 : 0};
-  for (size_t i = 0; i < cap && i < 4; ++i) out[i] = v[i];
+  const int32_t v[5] = {op->fused ? 1 : 0, op->cb, (op->fused ? op->ftk2 : op->tk2) ? 1 : 0, op->tuned ? 1 : 0,
+                        op->use_w1 && !op->fused ? 1 : 0};
+  for (size_t i = 0; i < cap && i < 5; ++i) out[i] = v[i];
   return TFMM_OK;
 }
 

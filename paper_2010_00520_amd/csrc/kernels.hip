@@ -145,6 +145,7 @@ hipError_t launch_zstage(const ZArgs& a, hipStream_t st, bool* supported) {
   switch (a.fmt) {
     case ZF_FULL: return launch_zstage_fmt<ZF_FULL>(a, st, supported);
     case ZF_TUCKER: return launch_zstage_fmt<ZF_TUCKER>(a, st, supported);
+    case ZF_TUCKER_W1: return launch_zstage_fmt<ZF_TUCKER_W1>(a, st, supported);
     case ZF_TT3D: return launch_zstage_fmt<ZF_TT3D>(a, st, supported);
     case ZF_TT4D: return launch_zstage_fmt<ZF_TT4D>(a, st, supported);
   }
@@ -177,13 +178,13 @@ size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1,
   return e * sizeof(float2);
 }
 
-size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf) {
+size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w1) {
   TuckerLds L;
   if (bf)
     L.plan<true>(qt / n2, n2, n3, r1, r2);
   else
     L.plan<false>(qt / n2, n2, n3, r1, r2);
-  return (size_t)L.total * sizeof(float2);
+  return (size_t)(w1 ? L.total_w1 : L.total) * sizeof(float2);
 }
 
 // ---------------------------------------------------------------------------

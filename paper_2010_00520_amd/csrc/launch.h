@@ -6,7 +6,11 @@
 namespace tfmm {
 
 // Operator family seen by the z-stage kernel.
-enum ZFmt { ZF_FULL = 0, ZF_TUCKER = 1, ZF_TT3D = 2, ZF_TT4D = 3 };
+// ZF_TUCKER_W1: Tucker-family restoration whose first product, the x-mode
+// product W1[fx][b][c] = sum_a U1[fx][a] C[a][b][c], was formed beforehand for
+// a chunk of directions (the 4-D formats, whose per-direction cores are
+// themselves formed per call); the z-stage starts from the second product.
+enum ZFmt { ZF_FULL = 0, ZF_TUCKER = 1, ZF_TT3D = 2, ZF_TT4D = 3, ZF_TUCKER_W1 = 4 };
 
 // Per-direction restoration descriptor (8 ints, float2 offsets):
 //   Tucker : offC, offU1, offU2, offU3, r1, r2, r3, 0     (C may live in scratch)
@@ -18,7 +22,8 @@ struct ZArgs {
   int p0, nrhs, ndl;          // first direction, RHS count, directions in this launch
   float2* H;                  // x-FFT'ed planes G [nrhs][ndl][n1][n2/2][K3]
   const float4* Tfull;        // FULL: [n_dir][n3/2][nq] (consecutive fz pairs)
-  const float2* cbase;        // cores (op data or scratch)
+  const float2* cbase;        // cores (op data or scratch); ZF_TUCKER_W1: W1 of directions p0.. (scratch)
+  long long w1dir;            // ZF_TUCKER_W1: W1 elements per direction (n1 r2 r3)
   const float2* fbase;        // factors (op data)
   const float2* wbase;        // TT-4D: T1 [nq][r2] (scratch)
   const float2* vbase;        // TT-4D: V [n_dir][n3][r2] (scratch)
@@ -53,7 +58,7 @@ inline size_t zplanes_lds_bytes(int n3, int cb, int rg) {
   return (qt * (n3 + 1) + (size_t)rg * qt * kp) * 8;
 }
 // LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
-size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf);
+size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w1 = false);
 
 // Per-RHS base pointers of one launch: rhs s reads A_s[n_dir][Kx][Ky][Kz] and
 // writes B_s of the same shape (complex64).  Passed by value.

@@ -173,7 +173,11 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
   } else {
     const int* d = a.desc + 8 * p;
     const int KC = a.KC, kcs = 31 - __builtin_clz(KC);  // KC is a power of two
-    if constexpr (FMT == ZF_TUCKER) {
+    if constexpr (FMT == ZF_TUCKER_W1) {
+      restore_tucker_w1<T, CB, NW, BF>(acc, a, d, p, q0, lds);
+      (void)KC;
+      (void)kcs;
+    } else if constexpr (FMT == ZF_TUCKER) {
       if (a.tk2) {
         restore_tucker<T, CB, NW, BF, N2C>(acc, a, d, q0, lds);
         return;

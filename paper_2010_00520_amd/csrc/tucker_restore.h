@@ -123,6 +123,7 @@ __device__ __forceinline__ void stq(float2* row, int k, float2 v) {
 // chunk, C chunk (rows padded to an even number of b), W1 chunk.
 struct TuckerLds {
   int s1, s2, fs, oU1, oU2, oV, oC, oW1, total;
+  int oW1b, total_w1;  // restoration from a formed W1: a second W1 buffer past `total`
   template <bool BF>
   __host__ __device__ __forceinline__ void plan(int nfx, int n2, int n3, int r1, int r2) {
     s1 = tk_stride<BF>(r1);
@@ -134,6 +135,8 @@ struct TuckerLds {
     oC = tk_align4(oV + 8 * n3);
     oW1 = tk_align4(oC + 8 * (r2 + (r2 & 1)) * s1);
     total = tk_align4(oW1 + nfx * fs);
+    oW1b = total;
+    total_w1 = tk_align4(oW1b + nfx * fs);
   }
 };
 
@@ -256,7 +259,10 @@ template <int T, int CB, int NW, bool BF, int N2C = 0>
 __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a, const int* d, int q0,
                                                float2* lds) {
   typedef Cx<BF> X;
-  constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T, PF = 4;
+  // PF: core elements per thread of a staging part.  Parts are loaded behind
+  // the column-block pairs of the second/third products; the 4-wave block has
+  // few pairs, so its parts are larger (fewer of them wait at the chunk end).
+  constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T, PF = NW >= 8 ? 4 : 8;
   constexpr bool kPairs = N2C > 0 && N2C % 32 == 0 && CB % 2 == 0;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, kg = l >> 4, i = l & 15, j = l & 15;
   const int n2 = N2C > 0 ? N2C : a.n2;
@@ -292,9 +298,20 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
   }
   if (r2 & 1)  // the padding b = r2 of the C chunk rows
     for (int e = tid; e < 8 * kp1; e += NT) stq<BF>(sC + (8 * r2 + e / kp1) * s1, e % kp1, make_float2(0.f, 0.f));
-  for (int e = tid; e < n2 * kp2; e += NT) {
-    const int fy = e / kp2, k = e - fy * kp2;
-    stq<BF>(sU2 + fy * s2, k, k < r2 ? U2[fy * r2 + k] : make_float2(0.f, 0.f));
+  // U2 rows in batches of 4 per thread: the loads of a batch are in flight
+  // together rather than one round trip per element
+  for (int e0 = tid; e0 < n2 * kp2; e0 += 4 * NT) {
+    float2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * NT, fy = e / kp2, k = e - fy * kp2;
+      v[u] = (e < n2 * kp2 && k < r2) ? U2[fy * r2 + k] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * NT, fy = e / kp2, k = e - fy * kp2;
+      if (e < n2 * kp2) stq<BF>(sU2 + fy * s2, k, v[u]);
+    }
   }
   if (kp1 > r1)
     for (int e = tid; e < 8 * r2 * (kp1 - r1); e += NT) {
@@ -409,20 +426,63 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
         const int fxc0 = min(j, nfx - 1), fxc1 = min(16 + j, nfx - 1);
         const float2* pb0 = sU1 + fxc0 * s1;
         const float2* pb1 = sU1 + fxc1 * s1;
-        for (int b = w; b < r2; b += NW) {
-          const float2* pa = sC + (8 * b + (i >> 1)) * s1;
-          v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
-          if (nfx > 16)
-            tk_kloop<BF, BF ? 1 : 4, true>(pa, pb0, pb1, ks1, D0, D1);
-          else
-            tk_kloop<BF, BF ? 1 : 4, false>(pa, pb0, pb1, ks1, D0, D1);
+        auto put1 = [&](const v4f& D, int b) {
           if (j < nfx) {
-            stq<BF>(sW1 + j * fs + 2 * kg * s2, b, make_float2(D0[0], D0[1]));
-            stq<BF>(sW1 + j * fs + (2 * kg + 1) * s2, b, make_float2(D0[2], D0[3]));
+            stq<BF>(sW1 + j * fs + 2 * kg * s2, b, make_float2(D[0], D[1]));
+            stq<BF>(sW1 + j * fs + (2 * kg + 1) * s2, b, make_float2(D[2], D[3]));
           }
-          if (16 + j < nfx) {
-            stq<BF>(sW1 + (16 + j) * fs + 2 * kg * s2, b, make_float2(D1[0], D1[1]));
-            stq<BF>(sW1 + (16 + j) * fs + (2 * kg + 1) * s2, b, make_float2(D1[2], D1[3]));
+        };
+        if (nfx > 16 || ks1 > 4) {
+          for (int b = w; b < r2; b += NW) {
+            const float2* pa = sC + (8 * b + (i >> 1)) * s1;
+            v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
+            if (nfx > 16)
+              tk_kloop<BF, BF ? 1 : 4, true>(pa, pb0, pb1, ks1, D0, D1);
+            else
+              tk_kloop<BF, BF ? 1 : 4, false>(pa, pb0, pb1, ks1, D0, D1);
+            put1(D0, b);
+            if (16 + j < nfx) {
+              stq<BF>(sW1 + (16 + j) * fs + 2 * kg * s2, b, make_float2(D1[0], D1[1]));
+              stq<BF>(sW1 + (16 + j) * fs + (2 * kg + 1) * s2, b, make_float2(D1[2], D1[3]));
+            }
+          }
+        } else {
+          // one fx tile: its U1 fragments (at most 4 K-steps, r1 <= 64) are
+          // the same for every b and stay in registers; two b per pass give
+          // two independent accumulation chains
+          typename X::B bu[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            if (s < ks1) bu[s] = X::load_b(pb0 + s * X::KS, kg);
+          const int ri = i & 1;
+          int b = w;
+          for (; b + NW < r2; b += 2 * NW) {
+            const float2* pa0 = sC + (8 * b + (i >> 1)) * s1;
+            const float2* pa1 = pa0 + 8 * NW * s1;
+            typename X::A a0[4], a1[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (s < ks1) {
+                a0[s] = X::load_a(pa0 + s * X::KS, kg, ri);
+                a1[s] = X::load_a(pa1 + s * X::KS, kg, ri);
+              }
+            v4f D0 = {0.f, 0.f, 0.f, 0.f}, D1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (s < ks1) {
+                D0 = X::mma(a0[s], bu[s], D0);
+                D1 = X::mma(a1[s], bu[s], D1);
+              }
+            put1(D0, b);
+            put1(D1, b + NW);
+          }
+          if (b < r2) {
+            const float2* pa0 = sC + (8 * b + (i >> 1)) * s1;
+            v4f D0 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+              if (s < ks1) D0 = X::mma(X::load_a(pa0 + s * X::KS, kg, ri), bu[s], D0);
+            put1(D0, b);
           }
         }
       }
@@ -536,6 +596,206 @@ __device__ __forceinline__ void restore_tucker(v4f (&acc)[T][CB], const ZArgs& a
       if (++part < nparts) load_part(part, c0 + 8);
     }
     __syncthreads();
+  }
+}
+
+// Restoration from a formed x-mode product W1[fx][b][c] (ZF_TUCKER_W1, the
+// 4-D formats on the three-pass path): only the second and third products run
+// here.  W1 chunks of 8 columns c alternate between two LDS buffers, the next
+// chunk staged while the current one feeds the second product.  The split of
+// (fx, b) by r2 is a multiply-high by ceil(2^32 / r2), exact for fx * r2 + b <
+// 2^16 and r2 <= 512.
+template <int T, int CB, int NW, bool BF>
+__device__ __forceinline__ void restore_tucker_w1(v4f (&acc)[T][CB], const ZArgs& a, const int* d, int p, int q0,
+                                                  float2* lds) {
+  typedef Cx<BF> X;
+  constexpr int NT = 64 * NW, QT = 16 * CB * NW, N3 = 8 * T, PF = 8;
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int n2 = a.n2;
+  const int r2 = d[5], r3 = d[6];
+  const float2* W1g = a.cbase + (long long)(p - a.p0) * a.w1dir;  // [fx][b][c]
+  const float2* U2 = a.fbase + d[2];
+  const float2* U3 = a.fbase + d[3];
+  const int nfx = QT / n2, fx0 = q0 / n2;
+  TuckerLds L;
+  L.plan<BF>(nfx, n2, N3, d[4], r2);
+  const int s2 = L.s2, fs = L.fs, kp2 = tk_kpad<BF>(r2);
+  const int ks2 = kp2 / X::KS;
+  float2* sU2 = lds + L.oU2;
+  float2* sV = lds + L.oV;
+  float2* sWa = lds + L.oW1;
+  float2* sWb = lds + L.oW1b;
+
+  for (int e0 = tid; e0 < n2 * kp2; e0 += 4 * NT) {
+    float2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * NT, fy = e / kp2, k = e - fy * kp2;
+      v[u] = (e < n2 * kp2 && k < r2) ? U2[fy * r2 + k] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * NT, fy = e / kp2, k = e - fy * kp2;
+      if (e < n2 * kp2) stq<BF>(sU2 + fy * s2, k, v[u]);
+    }
+  }
+  if (kp2 > r2)  // zero padding k = r2 .. kp2 - 1 of the W1 rows of both buffers (never rewritten)
+    for (int e = tid; e < 2 * 8 * nfx * (kp2 - r2); e += NT) {
+      const int row = e / (kp2 - r2), k = r2 + (e - row * (kp2 - r2));
+      float2* sw = row < 8 * nfx ? sWa : sWb;
+      const int rr = row < 8 * nfx ? row : row - 8 * nfx;
+      stq<BF>(sw + (rr >> 3) * fs + (rr & 7) * s2, k, make_float2(0.f, 0.f));
+    }
+
+  // W1 chunk element e = (fx * r2 + b) * 8 + cl  <-  W1[fx0 + fx][b][c0 + cl]
+  // (eight consecutive c of one (fx, b) are one contiguous run)
+  const int wsz = nfx * 8 * r2;
+  const unsigned m1 = (unsigned)(((1ull << 32) + (unsigned)r2 - 1) / (unsigned)r2);
+  constexpr int PART = PF * NT, VP = (8 * N3 + NT - 1) / NT;
+  const int nparts = (wsz + PART - 1) / PART;
+  float px[PF], py[PF], vx[VP], vy[VP];
+  auto split_e = [&](int e, int& fx, int& cl, int& b) {
+    const int fb = e >> 3;
+    cl = e & 7;
+    fx = (int)__umulhi((unsigned)fb, m1);
+    b = fb - fx * r2;
+  };
+  auto load_w = [&](int P, int c0) {
+    const int kc = min(8, r3 - c0);
+    int to = tid;
+    asm volatile("" : "+v"(to));
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = P * PART + to + u * NT;
+      int fx, cl, b;
+      split_e(e, fx, cl, b);
+      const float2 v = (e < wsz && cl < kc) ? W1g[((long long)fx0 * r2 + (e >> 3)) * r3 + c0 + cl]
+                                            : make_float2(0.f, 0.f);
+      px[u] = v.x;
+      py[u] = v.y;
+    }
+  };
+  auto store_w = [&](int P, float2* sw) {
+    int to = tid;
+    asm volatile("" : "+v"(to));
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = P * PART + to + u * NT;
+      if (e < wsz) {
+        int fx, cl, b;
+        split_e(e, fx, cl, b);
+        stq<BF>(sw + fx * fs + cl * s2, b, make_float2(px[u], py[u]));
+      }
+    }
+  };
+  auto load_v = [&](int c0) {
+    int to = tid;
+    asm volatile("" : "+v"(to));
+#pragma unroll
+    for (int u = 0; u < VP; ++u) {
+      const int e = to + u * NT, fz = e >> 3, cl = e & 7;
+      const float2 v = (e < 8 * N3 && c0 + cl < r3) ? U3[fz * r3 + c0 + cl] : make_float2(0.f, 0.f);
+      vx[u] = v.x;
+      vy[u] = v.y;
+    }
+  };
+  auto store_v = [&]() {
+#pragma unroll
+    for (int u = 0; u < VP; ++u) {
+      const int e = tid + u * NT;
+      if (e < 8 * N3) stq<BF>(sV + (e & ~7), e & 7, make_float2(vx[u], vy[u]));
+    }
+  };
+  load_v(0);
+  store_v();
+  for (int P = 0; P < nparts; ++P) {
+    load_w(P, 0);
+    store_w(P, sWa);
+  }
+  __syncthreads();
+
+  float a3f[T][BF ? 1 : 4];
+  v4u a3b[T];
+  const int nch = (r3 + 7) >> 3;
+  for (int h = 0; h < nch; ++h) {
+    const int c0 = 8 * h;
+    const bool more = h + 1 < nch;
+    const float2* cur = (h & 1) ? sWb : sWa;
+    float2* nxt = (h & 1) ? sWa : sWb;
+    int lo = tid & 63;
+    asm volatile("" : "+v"(lo));
+    const int kg = lo >> 4, i = lo & 15, j = lo & 15;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int fz = 8 * t + (i >> 1), ri = i & 1;
+      if constexpr (BF) {
+        const uint2* pv = reinterpret_cast<const uint2*>(reinterpret_cast<const unsigned*>(sV + fz * 8) +
+                                                         8 * (kg >> 1) + 2 * (kg & 1));
+        const uint2 vh = pv[0], vl = pv[2];
+        a3b[t] = v4u{embed_a_bf(vh.x, ri), embed_a_bf(vh.y, ri), embed_a_bf(vl.x, ri), embed_a_bf(vl.y, ri)};
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) a3f[t][s4] = embed_a(sV[fz * 8 + 2 * kg + (s4 >> 1)], ri, s4 & 1);
+      }
+    }
+    if (more) {
+      load_v(c0 + 8);
+      load_w(0, c0 + 8);
+    }
+    __syncthreads();  // every wave holds its U3 fragments: sV may be rewritten
+    int part = 0;     // part of the next chunk currently in registers
+    if (more) {
+      store_w(0, nxt);
+      store_v();
+      if (++part < nparts) load_w(part, c0 + 8);
+    }
+    auto finish = [&](int c, v4f D) {
+      if constexpr (BF) {
+        const uint2 e0 = split_bf3(make_float2(D[0], D[1])), e1 = split_bf3(make_float2(D[2], D[3]));
+        const v4u bh = v4u{e0.x, e1.x, e0.x, e1.x}, bl = v4u{e0.y, e1.y, 0u, 0u};
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+          acc[t][c] = mfma_bf16(a3b[t], bh, acc[t][c]);
+          acc[t][c] = mfma_bf16(a3b[t], bl, acc[t][c]);
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) acc[t][c] = mfma4(a3f[t][s4], D[s4], acc[t][c]);
+      }
+    };
+#pragma unroll
+    for (int c = 0; c < CB; c += 2) {
+      int fa[2], fb[2], fxj[2], fyj[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int qb = q0 + (w * CB + min(c + u, CB - 1)) * 16;
+        const int xa = qb / n2, off = qb - xa * n2 + j, wrap = off >= n2 ? 1 : 0;
+        fa[u] = xa - fx0;
+        fb[u] = (qb + 15) / n2 - fx0;
+        fxj[u] = fa[u] + wrap;
+        fyj[u] = off - wrap * n2;
+      }
+      if (c + 1 < CB && fa[0] == fb[0] && fa[1] == fb[1] && fa[0] == fa[1]) {
+        v4f D0, D1;
+        tk_wgemm2<BF>(cur, sU2, s2, fs, ks2, fa[0], fyj[0], fyj[1], D0, D1);
+        finish(c, D0);
+        finish(c + 1, D1);
+      } else {
+        finish(c, tk_wgemm<BF>(cur, sU2, s2, fs, ks2, fa[0], fb[0], fxj[0], fyj[0]));
+        if (c + 1 < CB) finish(c + 1, tk_wgemm<BF>(cur, sU2, s2, fs, ks2, fa[1], fb[1], fxj[1], fyj[1]));
+      }
+      if (more && part < nparts) {
+        store_w(part, nxt);
+        if (++part < nparts) load_w(part, c0 + 8);
+      }
+    }
+    while (more && part < nparts) {
+      store_w(part, nxt);
+      if (++part < nparts) load_w(part, c0 + 8);
+    }
+    __syncthreads();  // the next chunk is staged; this one is no longer read
   }
 }
 

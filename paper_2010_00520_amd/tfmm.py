@@ -221,10 +221,12 @@ class Operator:
         return inf.as_dict()
 
     def plan(self) -> dict:
-        """Current tile plan: fused path, three-pass cb, register-chained restoration, tuned."""
-        v = (ctypes.c_int32 * 4)()
-        _check(load().tfmm_op_plan(self.handle, v, 4))
-        return {"fused": bool(v[0]), "cb": int(v[1]), "register_chained": bool(v[2]), "tuned": bool(v[3])}
+        """Current tile plan: fused path, three-pass cb, register-chained restoration, tuned,
+        x-mode product formed ahead of the z-stage (4-D formats)."""
+        v = (ctypes.c_int32 * 5)()
+        _check(load().tfmm_op_plan(self.handle, v, 5))
+        return {"fused": bool(v[0]), "cb": int(v[1]), "register_chained": bool(v[2]), "tuned": bool(v[3]),
+                "w1_formed": bool(v[4])}
 
     def ranks(self) -> np.ndarray:
         need = ctypes.c_size_t()
