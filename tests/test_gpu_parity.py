@@ -358,3 +358,54 @@ def test_lossy_medium_translation(ctx, fmt):
         Th = O.fft_operator(O.sample_operator(K, 0.5, k_loss, L, khat[p:p + 1]))
         ref = O.translate_fft(A[:, p:p + 1].astype(np.complex128), Th)
         assert O.rel_l2(got[:, p:p + 1], ref) <= 10 * tol + 1e-6, p
+
+
+def _ctx_with_env(env):
+    import os
+
+    import paper_2010_00520_amd as P
+
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return P.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("K", [(16, 16, 16), (12, 12, 12)])
+@pytest.mark.parametrize("fmt", ["tucker4d", "htucker4d"])
+def test_formed_x_mode_product_restoration(fmt, K, prec):
+    """4-D formats on the three-pass path restore from the x-mode product
+    W1 = U1 x_1 C_p formed by a batched GEMM per direction chunk (Fig. 3(a) step
+    1 moved ahead of the z-stage); TFMM_NO_W1=1 keeps the product inside the
+    z-stage.  Both against the oracle, with an odd r2 and an r3 that leaves a
+    partial chunk of 8 core columns."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L = 3
+    n = tuple(2 * k for k in K)
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(seed_of("w1", fmt, K))
+    ranks = {"tucker4d": (9, 11, 13, 7), "htucker4d": (10, 9, 13, 8, 12, 11)}[fmt]
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    A = synth.gaussian_patterns((3, ndir) + K, seed_of("w1A", K))
+    ref = O.translate_compressed(A, comp)
+    tol = 1e-4 if prec == "bf16x3" else ARITH_TOL
+    for env, formed in (({"TFMM_NO_FUSED": "1"}, True), ({"TFMM_NO_FUSED": "1", "TFMM_NO_W1": "1"}, False)):
+        c = _ctx_with_env(env)
+        op = c.import_factors(K, L, fmt, rk, data, prec=prec)
+        plan = op.plan()
+        assert not plan["fused"] and plan["register_chained"] and plan["w1_formed"] == formed
+        got = gpu_translate(c, op, A)
+        assert O.rel_l2(got, ref) < tol, (formed, O.rel_l2(got, ref))
+        for s in range(A.shape[0]):
+            for p in (0, ndir // 2, ndir - 1):
+                assert O.rel_l2(got[s, p], ref[s, p]) < 5 * tol
+        op.release()
+        c.close()
