@@ -46,38 +46,75 @@ hipError_t launch_dipole_patterns(float4* pat, const double* khat, const double*
   return hipGetLastError();
 }
 
-// Eq. (4): A[2r + c][p][v] = sum_{n in B_v} g_c e I_r[orig(n)], one thread per
-// (box, direction); empty boxes get zero.
-__global__ void k_aggregate(const float4* __restrict__ pat, const int* __restrict__ start,
-                            const int* __restrict__ orig, const float2* __restrict__ I, float2* __restrict__ A, int N,
-                            int nbox, int ndir, int nrhs) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  const int p = blockIdx.y;
-  if (v >= nbox) return;
+// Eq. (4): A[2r + c][p][v] = sum_{n in B_v} g_c e I_r[orig(n)].  One wavefront
+// per (box v, group of kAggPG directions): its lanes stride over the box's
+// sorted range, so each table row is read as one contiguous run, the group's
+// rows are in flight together, and a butterfly sum per (direction, component)
+// leaves the box total in every lane.  Consecutive waves of a block take the
+// direction groups of one box (its currents stay in cache).  An empty box's
+// wave writes its zeros.
+constexpr int kAggPG = 8;
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_aggregate(const float4* __restrict__ pat, const int* __restrict__ start,
+                                                   const int* __restrict__ orig, const float2* __restrict__ I,
+                                                   float2* __restrict__ A, int N, int nbox, int ndir, int nrhs,
+                                                   int npg) {
+  const int l = threadIdx.x & 63;
+  const long long item = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= (long long)nbox * npg) return;
+  const int v = (int)(item / npg), p0 = (int)(item - (long long)v * npg) * kAggPG;
   const int b = start[v], e = start[v + 1];
-  const float4* row = pat + (size_t)p * N;
-  for (int r = 0; r < nrhs; ++r) {
-    float tr = 0.f, ti = 0.f, fr = 0.f, fi = 0.f;
-    const float2* Ir = I + (size_t)r * N;
-    for (int n = b; n < e; ++n) {
-      const float4 q = row[n];
-      const float2 cur = Ir[orig[n]];
-      // e * I
-      const float er = q.z * cur.x - q.w * cur.y, ei = q.z * cur.y + q.w * cur.x;
-      tr += q.x * er;
-      ti += q.x * ei;
-      fr += q.y * er;
-      fi += q.y * ei;
+  if (b == e) {
+    for (int t = l; t < kAggPG * 2 * nrhs; t += 64) {
+      const int k = t % kAggPG, rc = t / kAggPG;
+      if (p0 + k < ndir) A[((size_t)rc * ndir + p0 + k) * nbox + v] = make_float2(0.f, 0.f);
     }
-    A[((size_t)(2 * r) * ndir + p) * nbox + v] = make_float2(tr, ti);
-    A[((size_t)(2 * r + 1) * ndir + p) * nbox + v] = make_float2(fr, fi);
+    return;
+  }
+  for (int r = 0; r < nrhs; ++r) {
+    const float2* Ir = I + (size_t)r * N;
+    float tr[kAggPG], ti[kAggPG], fr[kAggPG], fi[kAggPG];
+#pragma unroll
+    for (int k = 0; k < kAggPG; ++k) tr[k] = ti[k] = fr[k] = fi[k] = 0.f;
+    for (int n = b + l; n < e; n += 64) {
+      const float2 cur = Ir[orig[n]];
+      float4 q[kAggPG];
+#pragma unroll
+      for (int k = 0; k < kAggPG; ++k)
+        q[k] = p0 + k < ndir ? pat[(size_t)(p0 + k) * N + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < kAggPG; ++k) {
+        // e * I, then the theta and phi components
+        const float er = q[k].z * cur.x - q[k].w * cur.y, ei = q[k].z * cur.y + q[k].w * cur.x;
+        tr[k] += q[k].x * er;
+        ti[k] += q[k].x * ei;
+        fr[k] += q[k].y * er;
+        fi[k] += q[k].y * ei;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kAggPG; ++k) {
+      const float a0 = wave_sum(tr[k]), a1 = wave_sum(ti[k]), a2 = wave_sum(fr[k]), a3 = wave_sum(fi[k]);
+      if (l == 0 && p0 + k < ndir) {
+        A[((size_t)(2 * r) * ndir + p0 + k) * nbox + v] = make_float2(a0, a1);
+        A[((size_t)(2 * r + 1) * ndir + p0 + k) * nbox + v] = make_float2(a2, a3);
+      }
+    }
   }
 }
 
 hipError_t launch_aggregate(const float4* pat, const int* start, const int* orig, const float2* I, float2* A, int N,
                             int nbox, int ndir, int nrhs, hipStream_t st) {
-  dim3 grid((nbox + 255) / 256, ndir);
-  hipLaunchKernelGGL(k_aggregate, grid, dim3(256), 0, st, pat, start, orig, I, A, N, nbox, ndir, nrhs);
+  const int npg = (ndir + kAggPG - 1) / kAggPG;
+  const long long waves = (long long)nbox * npg;
+  hipLaunchKernelGGL(k_aggregate, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, pat, start, orig, I, A, N,
+                     nbox, ndir, nrhs, npg);
   return hipGetLastError();
 }
 
@@ -93,20 +130,30 @@ __global__ void k_disaggregate(const float4* __restrict__ pat, const int* __rest
   float ar[RG], ai[RG];
 #pragma unroll
   for (int i = 0; i < RG; ++i) ar[i] = ai[i] = 0.f;
-  for (int p = 0; p < ndir; ++p) {
-    const float4 q = pat[(size_t)p * N + n];
-    // w_p / e = w_p conj(e) / |e|^2
-    const float s = w[p] / (q.z * q.z + q.w * q.w);
-    const float er = q.z * s, ei = -q.w * s;
+  // directions in groups of DG: the group's table loads are in flight together
+  constexpr int DG = 4;
+  for (int p0 = 0; p0 < ndir; p0 += DG) {
+    float4 q[DG];
 #pragma unroll
-    for (int i = 0; i < RG; ++i) {
-      if (i < nr) {
-        const int r = r0 + i;
-        const float2 bt = B[((size_t)(2 * r) * ndir + p) * nbox + v];
-        const float2 bf = B[((size_t)(2 * r + 1) * ndir + p) * nbox + v];
-        const float sr = q.x * bt.x + q.y * bf.x, si = q.x * bt.y + q.y * bf.y;
-        ar[i] += er * sr - ei * si;
-        ai[i] += er * si + ei * sr;
+    for (int k = 0; k < DG; ++k)
+      q[k] = p0 + k < ndir ? pat[(size_t)(p0 + k) * N + n] : make_float4(0.f, 0.f, 1.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < DG; ++k) {
+      const int p = p0 + k;
+      if (p >= ndir) break;
+      // w_p / e = w_p conj(e) / |e|^2
+      const float s = w[p] / (q[k].z * q[k].z + q[k].w * q[k].w);
+      const float er = q[k].z * s, ei = -q[k].w * s;
+#pragma unroll
+      for (int i = 0; i < RG; ++i) {
+        if (i < nr) {
+          const int r = r0 + i;
+          const float2 bt = B[((size_t)(2 * r) * ndir + p) * nbox + v];
+          const float2 bf = B[((size_t)(2 * r + 1) * ndir + p) * nbox + v];
+          const float sr = q[k].x * bt.x + q[k].y * bf.x, si = q[k].x * bt.y + q[k].y * bf.y;
+          ar[i] += er * sr - ei * si;
+          ai[i] += er * si + ei * sr;
+        }
       }
     }
   }
