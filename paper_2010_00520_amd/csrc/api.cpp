@@ -401,6 +401,12 @@ tfmm_status plan_zstage(tfmm_op op) {
         op->tk2 = true;
         need = need2;
       }
+    } else if (op->zfmt == tfmm::ZF_TT4D && !op->ctx->no_tk2 && ch.tk2 != 0) {
+      const size_t need2 = tfmm::tt4d_chained_lds_bytes(n3, r2, bf);
+      if (need2 <= lds_max) {
+        op->tk2 = true;
+        need = need2;
+      }
     }
     if (need > lds_max) return fail(TFMM_ERR_UNSUPPORTED, "ranks too large for the LDS-resident restoration");
     op->KC = KC;
@@ -429,6 +435,12 @@ tfmm_status plan_zstage(tfmm_op op) {
       rb = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, n1 * n2, KC, r1, r2);
       if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2 && ch.tk2 != 0) {
         const size_t rb2 = tfmm::tucker2_lds_bytes(n2, n3, n1 * n2, r1, r2, bf);
+        if (rb2 <= lds_max) {
+          ftk2 = true;
+          rb = rb2;
+        }
+      } else if (op->zfmt == tfmm::ZF_TT4D && !op->ctx->no_tk2 && ch.tk2 != 0) {
+        const size_t rb2 = tfmm::tt4d_chained_lds_bytes(n3, r2, bf);
         if (rb2 <= lds_max) {
           ftk2 = true;
           rb = rb2;
@@ -2002,7 +2014,7 @@ tfmm_status tfmm_autotune(tfmm_ctx c, tfmm_op op, int32_t nrhs, int32_t reps, in
   HIP_TRY(hipMemset(A, 0x3c, bytes));  // any finite pattern: the kernels' cost does not depend on values
   // candidates
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nq = n1 * n2;
-  const bool tucker = op->zfmt == tfmm::ZF_TUCKER;
+  const bool tucker = op->zfmt == tfmm::ZF_TUCKER || op->zfmt == tfmm::ZF_TT4D;  // register-chained or staged
   const bool fusable = !c->no_fused && n1 == n2 && n2 == n3 && (n1 == 8 || n1 == 16 || n1 == 24 || n1 == 32);
   std::vector<TuneChoice> cand;
   for (int tk : tucker ? std::vector<int>{1, 0} : std::vector<int>{-1}) {

@@ -178,6 +178,11 @@ size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1,
   return e * sizeof(float2);
 }
 
+size_t tt4d_chained_lds_bytes(int n3, int r2, bool bf) {
+  return (size_t)(bf ? tt4d_chained_lds_elems<true>(n3, r2) : tt4d_chained_lds_elems<false>(n3, r2)) *
+         sizeof(float2);
+}
+
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w1) {
   TuckerLds L;
   if (bf)

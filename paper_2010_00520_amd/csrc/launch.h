@@ -33,7 +33,7 @@ struct ZArgs {
   int cb;                     // column blocks per wave (pencil tile = 64*cb)
   int lds_bytes;              // dynamic LDS of the launch (0 for FULL)
   int bf;                     // 1: split-BF16 (bf16x3) restoration, 0: FP32
-  int tk2;                    // Tucker: 1 = register-chained restoration (tucker_restore.h)
+  int tk2;                    // Tucker, TT-4D: 1 = register-chained restoration (tucker_restore.h)
   int rg;                     // three-pass z-stage: RHS per group (half spectra held in LDS)
   // persistent launch: work items are taken from counter[0], counter[1]
   // counts finished blocks (both zero between launches; the last block
@@ -59,6 +59,9 @@ inline size_t zplanes_lds_bytes(int n3, int cb, int rg) {
 }
 // LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w1 = false);
+// LDS bytes of the TT-4D restoration with T1 read straight into MFMA operands
+// (V_p of one direction, n3 x r2 in chunks of 8 columns).
+size_t tt4d_chained_lds_bytes(int n3, int r2, bool bf);
 
 // Per-RHS base pointers of one launch: rhs s reads A_s[n_dir][Kx][Ky][Kz] and
 // writes B_s of the same shape (complex64).  Passed by value.

@@ -248,6 +248,10 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
         __syncthreads();
       }
     } else {  // ZF_TT4D: W = T1 (direction-independent), V = S_p (Fig. 4(b))
+      if (a.tk2) {
+        restore_tt4d_chained<T, CB, NW, BF>(acc, a, d, q0, lds);
+        return;
+      }
       const int r2 = d[5];
       const float2* V = a.vbase + d[3];
       const int oW = 0, oV = QT * KC;

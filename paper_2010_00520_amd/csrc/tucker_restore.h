@@ -799,4 +799,101 @@ __device__ __forceinline__ void restore_tucker_w1(v4f (&acc)[T][CB], const ZArgs
   }
 }
 
+// TT-4D restoration with the direction-independent T1[q][k] read straight into
+// MFMA B operands (Fig. 4(b): T~_p[fz][q] = sum_k V_p[fz][k] T1[q][k]).  The
+// whole V_p (n3 x r2) is staged once in LDS in chunks of 8 columns k (the
+// layout of the Tucker third product's A operand); per chunk, lane (kg, j) of
+// column block c loads T1[q_j][8h + 2kg .. + 1] from device memory, which is
+// exactly the B fragment the Tucker third product takes from its second
+// product.  No LDS staging of T1 and no block barrier inside the chunk loop.
+template <bool BF>
+__host__ __device__ __forceinline__ int tt4d_chained_lds_elems(int n3, int r2) {
+  return ((r2 + 7) >> 3) * 8 * n3;
+}
+
+template <int T, int CB, int NW, bool BF>
+__device__ __forceinline__ void restore_tt4d_chained(v4f (&acc)[T][CB], const ZArgs& a, const int* d, int q0,
+                                                     float2* lds) {
+  constexpr int NT = 64 * NW, N3 = 8 * T;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, kg = l >> 4, i = l & 15, j = l & 15;
+  const int r2 = d[5], nch = (r2 + 7) >> 3;
+  const float2* V = a.vbase + d[3];  // [n3][r2]
+  const float2* T1 = a.wbase;        // [nq][r2]
+  // sV chunk h, row fz: the 8 columns k = 8h .. 8h + 7 (zero past r2); loads
+  // in batches of 4 per thread
+  const int vsz = nch * 8 * N3;
+  for (int e0 = tid; e0 < vsz; e0 += 4 * NT) {
+    float2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * NT, h = e / (8 * N3), rem = e - h * 8 * N3, fz = rem >> 3, k = 8 * h + (rem & 7);
+      v[u] = (e < vsz && k < r2) ? V[fz * r2 + k] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = e0 + u * NT, h = e / (8 * N3), rem = e - h * 8 * N3;
+      if (e < vsz) stq<BF>(lds + h * 8 * N3 + (rem >> 3) * 8, rem & 7, v[u]);
+    }
+  }
+  __syncthreads();
+  const float2* rows[CB];
+  bool ok[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    const int q = q0 + (w * CB + c) * 16 + j;
+    ok[c] = q < a.nq;
+    rows[c] = T1 + (long long)(ok[c] ? q : 0) * r2;
+  }
+  auto load_b = [&](int h, float2 (&b)[CB][2]) {
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = 8 * h + 2 * kg + u;
+        b[c][u] = (ok[c] && k < r2) ? rows[c][k] : make_float2(0.f, 0.f);
+      }
+  };
+  float2 bcur[CB][2], bnxt[CB][2];
+  load_b(0, bcur);
+  for (int h = 0; h < nch; ++h) {
+    if (h + 1 < nch) load_b(h + 1, bnxt);
+    const float2* sV = lds + h * 8 * N3;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int fz = 8 * t + (i >> 1), ri = i & 1;
+      if constexpr (BF) {
+        const uint2* pv = reinterpret_cast<const uint2*>(reinterpret_cast<const unsigned*>(sV + fz * 8) +
+                                                         8 * (kg >> 1) + 2 * (kg & 1));
+        const uint2 vh = pv[0], vl = pv[2];
+        const v4u a3 = v4u{embed_a_bf(vh.x, ri), embed_a_bf(vh.y, ri), embed_a_bf(vl.x, ri), embed_a_bf(vl.y, ri)};
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          // [A_hi, A_lo] . [B_hi; B_hi] + [A_hi, A_lo] . [B_lo; 0]
+          const uint2 e0 = split_bf3(bcur[c][0]), e1 = split_bf3(bcur[c][1]);
+          acc[t][c] = mfma_bf16(a3, v4u{e0.x, e1.x, e0.x, e1.x}, acc[t][c]);
+          acc[t][c] = mfma_bf16(a3, v4u{e0.y, e1.y, 0u, 0u}, acc[t][c]);
+        }
+      } else {
+        float a3[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) a3[s4] = embed_a(sV[fz * 8 + 2 * kg + (s4 >> 1)], ri, s4 & 1);
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          acc[t][c] = mfma4(a3[0], bcur[c][0].x, acc[t][c]);
+          acc[t][c] = mfma4(a3[1], bcur[c][0].y, acc[t][c]);
+          acc[t][c] = mfma4(a3[2], bcur[c][1].x, acc[t][c]);
+          acc[t][c] = mfma4(a3[3], bcur[c][1].y, acc[t][c]);
+        }
+      }
+    }
+    if (h + 1 < nch) {
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        bcur[c][0] = bnxt[c][0];
+        bcur[c][1] = bnxt[c][1];
+      }
+    }
+  }
+}
+
 }  // namespace tfmm
