@@ -765,8 +765,9 @@ tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
     HIP_TRY(tfmm::launch_cgemm(n1, r2, r1, n2, GOp{D, r1, 1, 0}, GOp{D + oC1, (long long)n2 * r2, 1, r2}, T1,
                                (long long)n2 * r2, 1, r2, st));
     // V[p][z][b] = sum_c C2[b][z][c] U3[p][c]                  (Fig. 4(b) step 1, column p)
-    HIP_TRY(tfmm::launch_cgemm(n3, nd, r3, r2, GOp{D + oC2, r3, 1, (long long)n3 * r3}, GOp{D + oU3, 1, r3, 0}, V,
-                               r2, (long long)n3 * r2, 1, st));
+    // one GEMM per z (rows b, columns p), so each output column is a contiguous run of b
+    HIP_TRY(tfmm::launch_cgemm(r2, nd, r3, n3, GOp{D + oC2, (long long)n3 * r3, 1, r3}, GOp{D + oU3, 1, r3, 0}, V,
+                               1, (long long)n3 * r2, r2, st));
     L.done();
   }
   return TFMM_OK;

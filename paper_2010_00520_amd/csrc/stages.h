@@ -602,7 +602,17 @@ template <int FMT, int T, int CB, bool BF>
 __device__ __forceinline__ void zstage_item(const ZArgs& a, int it, float2* lds) {
   constexpr int NW = 4, QT = 16 * CB * NW;
   const int ntile = a.nq / QT;
-  const int pl = it / ntile, q0 = (it - pl * ntile) * QT;
+  // TT-4D restores every direction's tile from the same rows of T1: items run
+  // tile-major there, so the blocks resident together share those rows in L2
+  int pl, q0;
+  if constexpr (FMT == ZF_TT4D) {
+    const int tile = it / a.ndl;
+    pl = it - tile * a.ndl;
+    q0 = tile * QT;
+  } else {
+    pl = it / ntile;
+    q0 = (it - pl * ntile) * QT;
+  }
   const int p = a.perm ? a.perm[a.p0 + pl] : a.p0 + pl;
   v4f acc[T][CB];
   restore_tile<FMT, T, CB, NW, BF>(acc, a, p, q0, lds);
