@@ -115,8 +115,12 @@ def kernel_work(name, fmt, prec, ranks, info, K, n, ndir, nrhs, w1=False):
     three-pass path) the x-mode product n1 r1 r2 r3 per direction runs in its own
     batched GEMM (`a1_w1`) instead of the z-stage."""
     a1, a2 = restore_macs(fmt, ranks, n, ndir)
-    xmode = ndir * n[0] * ranks[0] * ranks[1] * ranks[2] if w1 else 0
-    if name == "a1_w1":
+    xmode = 0
+    if w1 and fmt == "tt3d":  # W_p = U1_p . C_p of every direction, formed by `a1_tt3d_w`
+        xmode = sum(n[0] * r1 * n[1] * r2 for r1, r2 in np.asarray(ranks).reshape(-1, 2))
+    elif w1:
+        xmode = ndir * n[0] * ranks[0] * ranks[1] * ranks[2]
+    if name in ("a1_w1", "a1_tt3d_w"):
         return 8.0 * xmode, 0.0, 0
     a2 -= xmode
     x, yz = fft_flops(K, n, ndir, nrhs)
@@ -600,8 +604,10 @@ def summarize(w, key, r, full, steps):
     kernels = {}
     for name, k in kt.items():
         per_step = k["launches"] / max(steps, 10)
-        work = kernel_work(name, fmt, prec, r["ranks"], info, w.K, w.n, w.n_dir, w.nrhs,
-                           w1=r.get("plan", {}).get("w1_formed", False))
+        plan = r.get("plan", {})
+        formed = plan.get("w1_formed", False) or (fmt == "tt3d" and plan.get("register_chained", False)
+                                                  and not plan.get("fused", False))
+        work = kernel_work(name, fmt, prec, r["ranks"], info, w.K, w.n, w.n_dir, w.nrhs, w1=formed)
         kernels[name] = {"avg_ms": k["avg_ms"], "launches_per_step": per_step,
                          **({"roofline": roofline_of(name, k["avg_ms"], work, prec)} if any(work) else {})}
     dom = max(kt, key=lambda n: kt[n]["avg_ms"] * kt[n]["launches"])

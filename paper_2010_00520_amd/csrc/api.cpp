@@ -97,6 +97,10 @@ struct tfmm_op_s {
   // direction's core is formed by a batched GEMM per direction chunk, and the
   // z-stage restores from it (ZF_TUCKER_W1)
   bool use_w1 = false;
+  // TT-3D on the three-pass path with register-chained restoration: the x-y
+  // products W_p[q][b] = sum_a U1_p[fx][a] C_p[a][fy][b] of every direction are
+  // formed by one batched GEMM per call (wtt_elems complex64 of scratch)
+  size_t wtt_elems = 0;
   size_t a1_bytes = 0;                 // scratch for per-direction cores (4-D formats)
   int* d_perm = nullptr;               // direction order, costliest restoration first (NULL: identity)
   float2* d_roots_z = nullptr;         // exp(-2 pi i m / n3), m < n3 (context table)
@@ -401,7 +405,7 @@ tfmm_status plan_zstage(tfmm_op op) {
         op->tk2 = true;
         need = need2;
       }
-    } else if (op->zfmt == tfmm::ZF_TT4D && !op->ctx->no_tk2 && ch.tk2 != 0) {
+    } else if ((op->zfmt == tfmm::ZF_TT4D || op->zfmt == tfmm::ZF_TT3D) && !op->ctx->no_tk2 && ch.tk2 != 0) {
       const size_t need2 = tfmm::tt4d_chained_lds_bytes(n3, r2, bf);
       if (need2 <= lds_max) {
         op->tk2 = true;
@@ -512,7 +516,7 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
       off = d[3] + (long long)n3 * r3;
     }
   } else if (op->fmt == TFMM_FMT_TT3D) {
-    long long off = 0;
+    long long off = 0, woff = 0;
     for (int p = 0; p < nd; ++p) {
       const int r1 = r[2 * p], r2 = r[2 * p + 1];
       int* d = &op->desc[8 * p];
@@ -521,7 +525,11 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
       d[3] = (int)(d[0] + (long long)r1 * n2 * r2);
       d[4] = r1; d[5] = r2;
       off = d[3] + (long long)n3 * r2;
+      d[7] = (int)woff;  // W_p = U1_p . C_p in the register-chained restoration's scratch
+      woff += (long long)n1 * n2 * r2;
     }
+    if (woff > INT32_MAX) return fail(TFMM_ERR_UNSUPPORTED, "TT-3D operator too large for the x-y product scratch");
+    op->wtt_elems = (size_t)woff;
   } else if (op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D) {
     const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3];
     long long oU1 = (op->fmt == TFMM_FMT_TUCKER4D) ? (long long)r1 * r2 * r3 * r4 : 0;
@@ -602,6 +610,7 @@ ScratchPlan scratch_plan(const tfmm_op_s* op, int nr_total, size_t cap) {
   sp.hbytes = (sp.hbytes + 255) / 256 * 256;
   sp.a1b = (op->a1_bytes + 255) / 256 * 256;
   sp.w1b = (w1_dir * sp.ndl + 255) / 256 * 256;
+  if (op->zfmt == tfmm::ZF_TT3D && op->tk2 && !op->fused) sp.w1b = (op->wtt_elems * sizeof(float2) + 255) / 256 * 256;
   return sp;
 }
 
@@ -797,6 +806,15 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
     tfmm_status s = run_a1(c, op, a1, st);
     if (s != TFMM_OK) return s;
   }
+  const bool tt3d_w = op->zfmt == tfmm::ZF_TT3D && op->tk2 && !op->fused;
+  if (tt3d_w) {
+    // W_p[q][b] = sum_a U1_p[fx][a] C_p[a][fy][b] for every direction (Fig. 4(a) step 1)
+    int r2max = 1;
+    for (int p = 0; p < nd; ++p) r2max = std::max(r2max, op->desc[8 * p + 5]);
+    Launch L(c, st, "a1_tt3d_w");
+    HIP_TRY(tfmm::launch_cgemm_tt3d(n1, n2, n2 * r2max, nd, op->d_desc, op->d_data, W1, st));
+    L.done();
+  }
   float2* roots = op->d_roots_z;
   float2* twx = op->d_roots_x;
   tfmm::ZArgs z{};
@@ -811,7 +829,7 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
     z.cbase = W1;
     z.w1dir = (long long)w1_elems_per_dir(op);
   }
-  z.wbase = a1;
+  z.wbase = tt3d_w ? W1 : a1;
   z.vbase = a1 + (op->fmt == TFMM_FMT_TT4D ? (size_t)op->nq * op->host.ranks[1] : 0);
   z.desc = op->d_desc;
   z.roots = roots;
@@ -2015,7 +2033,7 @@ tfmm_status tfmm_autotune(tfmm_ctx c, tfmm_op op, int32_t nrhs, int32_t reps, in
   HIP_TRY(hipMemset(A, 0x3c, bytes));  // any finite pattern: the kernels' cost does not depend on values
   // candidates
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nq = n1 * n2;
-  const bool tucker = op->zfmt == tfmm::ZF_TUCKER || op->zfmt == tfmm::ZF_TT4D;  // register-chained or staged
+  const bool tucker = op->zfmt != tfmm::ZF_FULL;  // register-chained or LDS-staged restoration
   const bool fusable = !c->no_fused && n1 == n2 && n2 == n3 && (n1 == 8 || n1 == 16 || n1 == 24 || n1 == 32);
   std::vector<TuneChoice> cand;
   for (int tk : tucker ? std::vector<int>{1, 0} : std::vector<int>{-1}) {

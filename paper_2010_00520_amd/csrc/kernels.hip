@@ -202,9 +202,21 @@ size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w
 // [[re, -im], [im, re]], B stacked (k, re/im); a lane's A fragment is one
 // float picked by address (component ri ^ ki) with the sign applied by xor.
 // ---------------------------------------------------------------------------
-template <int TM, int TN, int WGM, int WGN>
-__global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, GOp A, GOp B, float2* __restrict__ C,
-                                               long long cs0, long long cs1, long long csb, int tiles_n) {
+// With DESC, batch p takes its sizes and operands from the TT-3D descriptor
+// desc[8p]: W_p[fx][(fy, b)] = sum_a U1_p[fx][a] C_p[a][(fy, b)] (Fig. 4(a) step
+// 1), K = r1_p, N = n2 r2_p, A = U1_p at fbase + d[1], B = C_p at fbase + d[0],
+// C = W_p at wout + d[7] (row-major); blocks past the batch's N leave at once.
+struct GDesc {
+  const int* desc;
+  const float2* fbase;
+  float2* wout;
+  int n2;
+};
+
+template <int TM, int TN, int WGM, int WGN, bool DESC>
+__global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GOp B_, float2* __restrict__ C_,
+                                               long long cs0_, long long cs1_, long long csb_, int tiles_n,
+                                               GDesc G) {
   static_assert(WGM * WGN == 4, "four waves per block");
   constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN, KC = 16;
   constexpr int AS = KC + 1;                          // A row stride (complex)
@@ -216,6 +228,22 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, GOp A, GOp B
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int tmb = blockIdx.x / tiles_n, tnb = blockIdx.x - tmb * tiles_n;
   const int m0 = tmb * BM, n0 = tnb * BN;
+  int N = N_, K = K_;
+  GOp A = A_, B = B_;
+  float2* C = C_;
+  long long cs0 = cs0_, cs1 = cs1_, csb = csb_;
+  if constexpr (DESC) {
+    const int* d = G.desc + 8 * blockIdx.y;
+    K = d[4];
+    N = G.n2 * d[5];
+    if (n0 >= N) return;
+    A = GOp{G.fbase + d[1], K, 1, 0};
+    B = GOp{G.fbase + d[0], N, 1, 0};
+    C = G.wout + d[7];
+    cs0 = N;
+    cs1 = 1;
+    csb = 0;
+  }
   const float2* __restrict__ Ap = A.p + (long long)blockIdx.y * A.sb;
   const float2* __restrict__ Bp = B.p + (long long)blockIdx.y * B.sb;
   // global -> register staging: the contiguous index of each operand varies
@@ -303,14 +331,24 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N, int K, GOp A, GOp B
     }
 }
 
-template <int TM, int TN, int WGM, int WGN>
+template <int TM, int TN, int WGM, int WGN, bool DESC = false>
 static hipError_t run_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
-                            long long csb, hipStream_t st) {
+                            long long csb, hipStream_t st, GDesc G = GDesc{nullptr, nullptr, nullptr, 0}) {
   constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN;
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-  hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN>), dim3((unsigned)(tiles_m * tiles_n), (unsigned)nb), dim3(256), 0,
-                     st, M, N, K, A, B, C, cs0, cs1, csb, tiles_n);
+  hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN, DESC>), dim3((unsigned)(tiles_m * tiles_n), (unsigned)nb), dim3(256),
+                     0, st, M, N, K, A, B, C, cs0, cs1, csb, tiles_n, G);
   return hipGetLastError();
+}
+
+hipError_t launch_cgemm_tt3d(int n1, int n2, int nmax, int nd, const int* desc, const float2* fbase, float2* wout,
+                             hipStream_t st) {
+  if (n1 <= 0 || nmax <= 0 || nd <= 0) return hipSuccess;
+  if (nd > 65535) return hipErrorInvalidValue;
+  const GDesc G{desc, fbase, wout, n2};
+  const GOp none{nullptr, 0, 0, 0};
+  if (n1 <= 16) return run_cgemm<2, 2, 1, 4, true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
+  return run_cgemm<4, 2, 2, 2, true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
 }
 
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,

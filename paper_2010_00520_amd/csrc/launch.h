@@ -25,7 +25,7 @@ struct ZArgs {
   const float2* cbase;        // cores (op data or scratch); ZF_TUCKER_W1: W1 of directions p0.. (scratch)
   long long w1dir;            // ZF_TUCKER_W1: W1 elements per direction (n1 r2 r3)
   const float2* fbase;        // factors (op data)
-  const float2* wbase;        // TT-4D: T1 [nq][r2] (scratch)
+  const float2* wbase;        // TT-4D: T1 [nq][r2]; register-chained TT-3D: W_p [nq][r2_p] at desc[7] (scratch)
   const float2* vbase;        // TT-4D: V [n_dir][n3][r2] (scratch)
   const int* desc;            // [n_dir][8]
   const float2* roots;        // exp(-2 pi i m / n3), m < n3 (FP64-built, rounded)
@@ -103,6 +103,11 @@ struct GOp {
 };
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                         long long csb, hipStream_t st);
+// TT-3D: W_p[q][b] = sum_a U1_p[fx][a] C_p[a][fy][b] for every direction p
+// (q = fx n2 + fy; per-direction ranks from desc[8p + 4], desc[8p + 5]; W_p at
+// wout + desc[8p + 7]); nmax = n2 * max r2.
+hipError_t launch_cgemm_tt3d(int n1, int n2, int nmax, int nd, const int* desc, const float2* fbase, float2* wout,
+                             hipStream_t st);
 
 // FP64 operator sampling, Eq. (7): T[p][m1][m2][m3] (double2) for every direction,
 // wavenumber k = kre + i kim.

@@ -219,6 +219,10 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
         __syncthreads();
       }
     } else if constexpr (FMT == ZF_TT3D) {
+      if (a.tk2) {  // W_p formed ahead of the z-stage (launch_cgemm_tt3d)
+        restore_tt_chained<T, CB, NW, BF>(acc, a, d[5], a.fbase + d[3], a.wbase + d[7], q0, lds);
+        return;
+      }
       const int r1 = d[4], r2 = d[5];
       const float2* C = a.cbase + d[0];
       const float2* U1 = a.fbase + d[1];
@@ -249,7 +253,7 @@ __device__ __forceinline__ void restore_tile(v4f (&acc)[T][CB], const ZArgs& a, 
       }
     } else {  // ZF_TT4D: W = T1 (direction-independent), V = S_p (Fig. 4(b))
       if (a.tk2) {
-        restore_tt4d_chained<T, CB, NW, BF>(acc, a, d, q0, lds);
+        restore_tt_chained<T, CB, NW, BF>(acc, a, d[5], a.vbase + d[3], a.wbase, q0, lds);
         return;
       }
       const int r2 = d[5];

@@ -799,26 +799,27 @@ __device__ __forceinline__ void restore_tucker_w1(v4f (&acc)[T][CB], const ZArgs
   }
 }
 
-// TT-4D restoration with the direction-independent T1[q][k] read straight into
-// MFMA B operands (Fig. 4(b): T~_p[fz][q] = sum_k V_p[fz][k] T1[q][k]).  The
-// whole V_p (n3 x r2) is staged once in LDS in chunks of 8 columns k (the
-// layout of the Tucker third product's A operand); per chunk, lane (kg, j) of
-// column block c loads T1[q_j][8h + 2kg .. + 1] from device memory, which is
-// exactly the B fragment the Tucker third product takes from its second
-// product.  No LDS staging of T1 and no block barrier inside the chunk loop.
+// TT restoration T~_p[fz][q] = sum_k V[fz][k] W[q][k] with W read straight
+// into MFMA B operands: TT-4D (Fig. 4(b)) with V = V_p (a1) and W = T1, the
+// direction-independent x-y product; TT-3D (Fig. 4(a)) with V = U3_p and W =
+// W_p, the per-direction x-y product formed ahead of the z-stage.  V (n3 x r2)
+// is staged once in LDS in chunks of 8 columns k (the layout of the Tucker
+// third product's A operand); per chunk, lane (kg, j) of column block c loads
+// W[q_j][8h + 2kg .. + 1] from device memory, which is exactly the B fragment
+// the Tucker third product takes from its second product.  No LDS staging of
+// W and no block barrier inside the chunk loop.
 template <bool BF>
 __host__ __device__ __forceinline__ int tt4d_chained_lds_elems(int n3, int r2) {
   return ((r2 + 7) >> 3) * 8 * n3;
 }
 
 template <int T, int CB, int NW, bool BF>
-__device__ __forceinline__ void restore_tt4d_chained(v4f (&acc)[T][CB], const ZArgs& a, const int* d, int q0,
-                                                     float2* lds) {
+__device__ __forceinline__ void restore_tt_chained(v4f (&acc)[T][CB], const ZArgs& a, int r2, const float2* V,
+                                                   const float2* T1, int q0, float2* lds) {
   constexpr int NT = 64 * NW, N3 = 8 * T;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, kg = l >> 4, i = l & 15, j = l & 15;
-  const int r2 = d[5], nch = (r2 + 7) >> 3;
-  const float2* V = a.vbase + d[3];  // [n3][r2]
-  const float2* T1 = a.wbase;        // [nq][r2]
+  const int nch = (r2 + 7) >> 3;
+  // V: [n3][r2]; T1 (W): [nq][r2]
   // sV chunk h, row fz: the 8 columns k = 8h .. 8h + 7 (zero past r2); loads
   // in batches of 4 per thread
   const int vsz = nch * 8 * N3;

@@ -268,11 +268,12 @@ def test_unsupported_grids_rejected(ctx):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("no_fused", ["0", "1"])
-@pytest.mark.parametrize("fmt", ["tucker3d", "tucker4d", "htucker4d"])
+@pytest.mark.parametrize("fmt", ["tucker3d", "tucker4d", "htucker4d", "tt3d", "tt4d"])
 def test_lds_staged_tucker_restoration(fmt, no_fused, prec):
-    """The Tucker family's LDS-staged restoration (block GEMMs through LDS, used
-    when a chunk of the register-chained one does not fit; TFMM_NO_TK2=1 forces
-    it) against the oracle, on the fused and the three-pass paths."""
+    """The LDS-staged restoration (block GEMMs through LDS, used when the
+    register-chained one does not fit; TFMM_NO_TK2=1 forces it) against the
+    oracle, on the fused and the three-pass paths, for the Tucker family and
+    the TT formats."""
     import os
 
     import paper_2010_00520_amd as P
@@ -283,7 +284,7 @@ def test_lds_staged_tucker_restoration(fmt, no_fused, prec):
     n = tuple(2 * k for k in K)
     ndir = (L + 1) * 2 * (L + 1)
     rng = np.random.default_rng(seed_of("staged", fmt))
-    ranks = {"tucker4d": (9, 11, 7, 13), "htucker4d": (8, 9, 7, 10, 12, 11)}.get(fmt)
+    ranks = {"tucker4d": (9, 11, 7, 13), "htucker4d": (8, 9, 7, 10, 12, 11), "tt4d": (7, 13, 9)}.get(fmt)
     rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
     old = {k: os.environ.get(k) for k in ("TFMM_NO_TK2", "TFMM_NO_FUSED")}
     os.environ["TFMM_NO_TK2"] = "1"
