@@ -360,8 +360,8 @@ tfmm_status tfmm_sched_stats(tfmm_ctx ctx, uint64_t* out, size_t cap);
 
 /* Time every tile configuration the operator's grid admits (fused
  * one-kernel path vs three-pass pipeline, three-pass pencil tile of 64*cb
- * pencils, and for Tucker-family operators the register-chained vs
- * LDS-staged restoration) on `nrhs` right-hand sides, `reps` timed runs each
+ * pencils, and for compressed operators the register-chained vs LDS-staged
+ * restoration) on `nrhs` right-hand sides, `reps` timed runs each
  * (median of HIP-event durations on an internal stream, after two warm-up
  * runs), and adopt the fastest for this operator.  Temporary A/B buffers
  * (2 x nrhs x n_dir x Kx x Ky x Kz complex64) are charged to the budget for
@@ -373,6 +373,10 @@ tfmm_status tfmm_sched_stats(tfmm_ctx ctx, uint64_t* out, size_t cap);
  * `choice_out` (may be NULL) receives {fused 0/1, cb, register-chained 0/1};
  * `best_ms` (may be NULL) the winning median.  TFMM_ERR_BUSY while submitted
  * jobs use the operator. */
+/* The first time one of the operator's batched GEMMs (per-direction cores,
+ * formed x-mode or x-y products) runs during this call, its shape's block tile
+ * and LDS buffering are chosen by timing each once; the choice is kept for
+ * the process (every choice gives bitwise-identical results). */
 tfmm_status tfmm_autotune(tfmm_ctx ctx, tfmm_op op, int32_t nrhs, int32_t reps, int32_t* choice_out,
                           double* best_ms);
 

@@ -2021,6 +2021,12 @@ tfmm_status tfmm_autotune(tfmm_ctx c, tfmm_op op, int32_t nrhs, int32_t reps, in
   std::lock_guard<std::recursive_mutex> g(c->mu);
   if (op->refs.load() > 0) return fail(TFMM_ERR_BUSY, "operator has queued jobs");
   HIP_TRY(hipSetDevice(c->device));
+  // the operator's GEMMs (a1 and the formed products) measure their tile
+  // configurations the first time they run in here
+  struct GemmTuning {
+    GemmTuning() { tfmm::set_gemm_tuning(true); }
+    ~GemmTuning() { tfmm::set_gemm_tuning(false); }
+  } gemm_tuning;
   const size_t bytes = (size_t)nrhs * op->ndir * op->K[0] * op->K[1] * op->K[2] * sizeof(float2);
   void *A = nullptr, *B = nullptr;
   tfmm_status s = dev_alloc(c, &A, bytes);

@@ -10,6 +10,11 @@
 //   setup   k_sample   FP64 operator samples, Eq. (7)
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "device_common.h"
 #include "launch.h"
 #include "tucker_restore.h"
@@ -196,8 +201,9 @@ size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w
 // a1: batched complex GEMM C[b] = A[b] B[b] (complex64, arbitrary element
 // strides), LDS-tiled on 16x16x4 f32 MFMAs.  A block of four waves owns a
 // BM x BN complex tile of C (waves arranged WGM x WGN, each TM x TN MFMA tiles
-// of 8 x 16 complex); K is staged in chunks of KC complex through LDS, the
-// next chunk prefetched into registers while the current one is multiplied.
+// of 8 x 16 complex); K is staged in chunks of KC complex through two LDS
+// buffers, the next chunk loaded into registers and stored into the idle
+// buffer while the current one is multiplied.
 // Real embedding as elsewhere: A rows (m, re/im) x k columns (k, re/im) of
 // [[re, -im], [im, re]], B stacked (k, re/im); a lane's A fragment is one
 // float picked by address (component ri ^ ki) with the sign applied by xor.
@@ -213,7 +219,7 @@ struct GDesc {
   int n2;
 };
 
-template <int TM, int TN, int WGM, int WGN, bool DESC>
+template <int TM, int TN, int WGM, int WGN, bool DESC, bool DB>
 __global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GOp B_, float2* __restrict__ C_,
                                                long long cs0_, long long cs1_, long long csb_, int tiles_n,
                                                GDesc G) {
@@ -223,8 +229,11 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GO
   constexpr int BS = BN + ((BN % 32) == 0 ? 16 : 0);  // B row stride: k rows of a fragment in other banks
   constexpr int EA = BM * KC / 256, EB = KC * BN / 256;
   static_assert(EA * 256 == BM * KC && EB * 256 == KC * BN, "whole tiles per thread");
-  __shared__ float2 sA[BM * AS];
-  __shared__ float2 sB[KC * BS];
+  // DB: two LDS buffers, chunk c multiplied out of one while chunk c + 1 is
+  // stored into the other (one block barrier per chunk); else one buffer and
+  // two barriers per chunk, half the LDS (more resident blocks)
+  __shared__ float2 sA[(DB ? 2 : 1) * BM * AS];
+  __shared__ float2 sB[(DB ? 2 : 1) * KC * BS];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int tmb = blockIdx.x / tiles_n, tnb = blockIdx.x - tmb * tiles_n;
   const int m0 = tmb * BM, n0 = tnb * BN;
@@ -272,18 +281,20 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GO
       rb[u] = (gk < K && gn < N) ? Bp[(long long)gk * B.s0 + (long long)gn * B.s1] : make_float2(0.f, 0.f);
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
+    float2* dA = sA + buf * (BM * AS);
+    float2* dB = sB + buf * (KC * BS);
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       int mm, kk;
       a_pos(tid + 256 * u, mm, kk);
-      sA[mm * AS + kk] = ra[u];
+      dA[mm * AS + kk] = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       int kk, nn;
       b_pos(tid + 256 * u, kk, nn);
-      sB[kk * BS + nn] = rb[u];
+      dB[kk * BS + nn] = rb[u];
     }
   };
   const int wm = w / WGN, wn = w - wm * WGN;
@@ -298,23 +309,39 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GO
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   const int nk = (K + KC - 1) / KC;
-  load(0);
-  for (int c = 0; c < nk; ++c) {
-    __syncthreads();  // the previous chunk's fragments have been read
-    store();
-    __syncthreads();
-    if (c + 1 < nk) load((c + 1) * KC);
+  auto chunk = [&](const float* fac, const float* fbc) {
 #pragma unroll
     for (int s = 0; s < KC / 2; ++s) {
       float af[TM], bf[TN];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) af[a] = __uint_as_float(__float_as_uint(fa[2 * (a * 8 * AS + 2 * s)]) ^ neg);
+      for (int a = 0; a < TM; ++a) af[a] = __uint_as_float(__float_as_uint(fac[2 * (a * 8 * AS + 2 * s)]) ^ neg);
 #pragma unroll
-      for (int b = 0; b < TN; ++b) bf[b] = fb[2 * (2 * s * BS + b * 16)];
+      for (int b = 0; b < TN; ++b) bf[b] = fbc[2 * (2 * s * BS + b * 16)];
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = mfma4(af[a], bf[b], acc[a][b]);
+    }
+  };
+  load(0);
+  if constexpr (DB) {
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nk; ++c) {
+      const int cur = c & 1;
+      if (c + 1 < nk) load((c + 1) * KC);  // in flight while chunk c is multiplied
+      chunk(fa + cur * (2 * BM * AS), fb + cur * (2 * KC * BS));
+      // the other buffer was last read in chunk c - 1, before the previous barrier
+      if (c + 1 < nk) store(cur ^ 1);
+      __syncthreads();
+    }
+  } else {
+    for (int c = 0; c < nk; ++c) {
+      __syncthreads();  // the previous chunk's fragments have been read
+      store(0);
+      __syncthreads();
+      if (c + 1 < nk) load((c + 1) * KC);
+      chunk(fa, fb);
     }
   }
   float2* Cb = C + (long long)blockIdx.y * csb;
@@ -331,14 +358,118 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GO
     }
 }
 
-template <int TM, int TN, int WGM, int WGN, bool DESC = false>
+template <int TM, int TN, int WGM, int WGN, bool DESC, bool DB>
 static hipError_t run_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
-                            long long csb, hipStream_t st, GDesc G = GDesc{nullptr, nullptr, nullptr, 0}) {
+                            long long csb, hipStream_t st, GDesc G) {
   constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN;
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-  hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN, DESC>), dim3((unsigned)(tiles_m * tiles_n), (unsigned)nb), dim3(256),
-                     0, st, M, N, K, A, B, C, cs0, cs1, csb, tiles_n, G);
+  hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN, DESC, DB>), dim3((unsigned)(tiles_m * tiles_n), (unsigned)nb),
+                     dim3(256), 0, st, M, N, K, A, B, C, cs0, cs1, csb, tiles_n, G);
   return hipGetLastError();
+}
+
+// Block tiles (BM x BN complex) the GEMMs choose from, each with one or two
+// LDS buffers.  Without a measured choice the tile minimises the padded work
+// divided by how well the launch fills the chip (a launch of fewer than 1024
+// blocks, four per compute unit, runs each block's K loop with little
+// company, so its cost is scaled up by 1024 / blocks), and two buffers are
+// used when K spans more than two chunks.  tfmm_autotune times every
+// configuration once per GEMM shape (all give bitwise-identical results: the
+// order of the K sum does not depend on the tile) and keeps the fastest.
+struct TileCfg {
+  int bm, bn;
+};
+static constexpr TileCfg kTiles[] = {{64, 64}, {48, 64}, {32, 64}, {32, 32}, {128, 16}, {16, 128}, {16, 64}};
+static constexpr int kNumTiles = (int)(sizeof(kTiles) / sizeof(kTiles[0]));
+
+static int pick_tile(int M, int N, int nb) {
+  int best = 0;
+  double bcost = 1e300;
+  for (int t = 0; t < kNumTiles; ++t) {
+    const long long tm = (M + kTiles[t].bm - 1) / kTiles[t].bm, tn = (N + kTiles[t].bn - 1) / kTiles[t].bn;
+    const double blocks = (double)tm * tn * nb;
+    const double padded = (double)tm * kTiles[t].bm * tn * kTiles[t].bn * nb;
+    const double cost = padded * std::max(1.0, 1024.0 / blocks);
+    if (cost < bcost * 0.999) {
+      bcost = cost;
+      best = t;
+    }
+  }
+  return best;
+}
+
+template <bool DESC, bool DB>
+static hipError_t run_cgemm_tile(int t, int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0,
+                                 long long cs1, long long csb, hipStream_t st, GDesc G) {
+  switch (t) {
+    case 0: return run_cgemm<4, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 64 x 64
+    case 1: return run_cgemm<3, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 48 x 64
+    case 2: return run_cgemm<2, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 32 x 64
+    case 3: return run_cgemm<2, 1, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 32 x 32
+    case 4: return run_cgemm<4, 1, 4, 1, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 128 x 16
+    case 5: return run_cgemm<2, 2, 1, 4, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 16 x 128
+    default: return run_cgemm<1, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);  // 16 x 64
+  }
+}
+
+// measured configuration per GEMM shape: index = tile * 2 + (two buffers)
+struct GemmKey {
+  int M, N, K, nb;
+  bool akf, bkf, desc;
+  bool operator<(const GemmKey& o) const {
+    return std::tie(M, N, K, nb, akf, bkf, desc) < std::tie(o.M, o.N, o.K, o.nb, o.akf, o.bkf, o.desc);
+  }
+};
+static std::mutex g_gemm_mu;
+static std::map<GemmKey, int> g_gemm_pick;
+static thread_local bool g_gemm_tuning = false;
+
+void set_gemm_tuning(bool on) { g_gemm_tuning = on; }
+
+template <bool DESC>
+static hipError_t run_cgemm_pick(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
+                                 long long csb, hipStream_t st, GDesc G) {
+  auto launch = [&](int cfg) {
+    return (cfg & 1) ? run_cgemm_tile<DESC, true>(cfg >> 1, M, N, K, nb, A, B, C, cs0, cs1, csb, st, G)
+                     : run_cgemm_tile<DESC, false>(cfg >> 1, M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);
+  };
+  // DESC: K per batch comes from the descriptor; the key uses the bound N and no K
+  const GemmKey key{M, N, DESC ? 0 : K, nb, A.s1 == 1, B.s0 == 1, DESC};
+  int cfg = -1;
+  {
+    std::lock_guard<std::mutex> g(g_gemm_mu);
+    auto it = g_gemm_pick.find(key);
+    if (it != g_gemm_pick.end()) cfg = it->second;
+  }
+  if (cfg < 0 && g_gemm_tuning) {
+    // time every configuration on this stream (eager launches, outside capture)
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+      float best = 1e30f;
+      for (int c = 0; c < 2 * kNumTiles; ++c) {
+        if (launch(c) != hipSuccess) continue;  // warm-up
+        (void)hipEventRecord(e0, st);
+        bool ok = true;
+        for (int r = 0; r < 3 && ok; ++r) ok = launch(c) == hipSuccess;
+        (void)hipEventRecord(e1, st);
+        float ms = 0.f;
+        if (ok && hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess &&
+            ms < best) {
+          best = ms;
+          cfg = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    (void)hipGetLastError();
+    if (cfg >= 0) {
+      std::lock_guard<std::mutex> g(g_gemm_mu);
+      g_gemm_pick[key] = cfg;
+    }
+  }
+  if (cfg < 0) cfg = pick_tile(M, N, nb) * 2 + (K > 32 ? 1 : 0);
+  return launch(cfg);
 }
 
 hipError_t launch_cgemm_tt3d(int n1, int n2, int nmax, int nd, const int* desc, const float2* fbase, float2* wout,
@@ -347,17 +478,14 @@ hipError_t launch_cgemm_tt3d(int n1, int n2, int nmax, int nd, const int* desc, 
   if (nd > 65535) return hipErrorInvalidValue;
   const GDesc G{desc, fbase, wout, n2};
   const GOp none{nullptr, 0, 0, 0};
-  if (n1 <= 16) return run_cgemm<2, 2, 1, 4, true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
-  return run_cgemm<4, 2, 2, 2, true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
+  return run_cgemm_pick<true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
 }
 
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                         long long csb, hipStream_t st) {
   if (M <= 0 || N <= 0 || nb <= 0) return hipSuccess;
   if (nb > 65535) return hipErrorInvalidValue;
-  if (N <= 16) return run_cgemm<4, 1, 4, 1>(M, N, K, nb, A, B, C, cs0, cs1, csb, st);   // 128 x 16
-  if (M <= 16) return run_cgemm<2, 2, 1, 4>(M, N, K, nb, A, B, C, cs0, cs1, csb, st);   // 16 x 128
-  return run_cgemm<4, 2, 2, 2>(M, N, K, nb, A, B, C, cs0, cs1, csb, st);                // 64 x 64
+  return run_cgemm_pick<false>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, GDesc{nullptr, nullptr, nullptr, 0});
 }
 
 }  // namespace tfmm

@@ -103,6 +103,9 @@ struct GOp {
 };
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                         long long csb, hipStream_t st);
+// While on (per thread), a GEMM shape without a measured tile configuration
+// times them all on its stream and keeps the fastest (tfmm_autotune).
+void set_gemm_tuning(bool on);
 // TT-3D: W_p[q][b] = sum_a U1_p[fx][a] C_p[a][fy][b] for every direction p
 // (q = fx n2 + fy; per-direction ranks from desc[8p + 4], desc[8p + 5]; W_p at
 // wout + desc[8p + 7]); nmax = n2 * max r2.
