@@ -394,16 +394,21 @@ tfmm_status plan_zstage(tfmm_op op) {
   const size_t lds_max = 160 * 1024 - 64;  // leaves room for the work-item slot
   const bool bf = op->prec == TFMM_PREC_BF16X3;
   op->tk2 = op->ftk2 = false;
+  int kfmt = op->zfmt;  // the z-stage kernel family this plan launches
   if (op->zfmt != tfmm::ZF_FULL) {
     const size_t cap = 96 * 1024;
     int KC = 16;
     while (KC > 1 && tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2) > cap) KC /= 2;
     size_t need = tfmm::zstage_lds_bytes(op->zfmt, n1, n2, n3, 64 * op->cb, KC, r1, r2);
     if (op->zfmt == tfmm::ZF_TUCKER && !op->ctx->no_tk2 && ch.tk2 != 0) {
-      const size_t need2 = tfmm::tucker2_lds_bytes(n2, n3, 64 * op->cb, r1, r2, bf);
+      // the 4-D formats restore from a formed x-mode product on this path
+      // (no core chunk in LDS), unless TFMM_NO_W1=1
+      const bool w1 = (op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D) && !op->ctx->no_w1;
+      const size_t need2 = tfmm::tucker2_lds_bytes(n2, n3, 64 * op->cb, r1, r2, bf, w1);
       if (need2 <= lds_max) {
         op->tk2 = true;
         need = need2;
+        if (w1) kfmt = tfmm::ZF_TUCKER_W1;
       }
     } else if ((op->zfmt == tfmm::ZF_TT4D || op->zfmt == tfmm::ZF_TT3D) && !op->ctx->no_tk2 && ch.tk2 != 0) {
       const size_t need2 = tfmm::tt4d_chained_lds_bytes(n3, r2, bf);
@@ -417,13 +422,26 @@ tfmm_status plan_zstage(tfmm_op op) {
     op->lds = (int)need;
   }
   // the z-stage's y- and z-stages reuse the restoration's LDS; RHS go through in
-  // groups of rg half spectra, as many as fit
-  op->rg = 1;
-  for (int rg : {4, 2})
-    if (tfmm::zplanes_lds_bytes(n3, op->cb, rg) <= lds_max) {
-      op->rg = rg;
-      break;
-    }
+  // groups of rg half spectra.  Where the kernel is built for two waves per
+  // SIMD (n3 <= 32), the largest group that lets two blocks share a compute
+  // unit's LDS comes first; otherwise as many as fit.
+  op->rg = 0;
+  if (tfmm::zplanes_waves_per_simd(kfmt, n3 / 8) == 2) {
+    const size_t two = 80 * 1024 - 64 - TFMM_LDS_SLOT;
+    for (int rg : {4, 2, 1})
+      if (std::max<size_t>((size_t)op->lds, tfmm::zplanes_lds_bytes(n3, op->cb, rg)) <= two) {
+        op->rg = rg;
+        break;
+      }
+  }
+  if (op->rg == 0) {
+    op->rg = 1;
+    for (int rg : {4, 2})
+      if (tfmm::zplanes_lds_bytes(n3, op->cb, rg) <= lds_max) {
+        op->rg = rg;
+        break;
+      }
+  }
   op->lds = (int)std::max<size_t>((size_t)op->lds, tfmm::zplanes_lds_bytes(n3, op->cb, op->rg));
   // fused path: cubic grids whose half spectrum (n*n*zp complex64) fits in LDS
   op->fused = false;
@@ -458,15 +476,9 @@ tfmm_status plan_zstage(tfmm_op op) {
       op->flds = (int)std::max(hbytes, rb);
     }
   }
-  op->use_w1 = false;
-  if ((op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D) && !op->fused && op->tk2 &&
-      !op->ctx->no_w1) {
-    const size_t need_w1 = tfmm::tucker2_lds_bytes(n2, n3, 64 * op->cb, r1, r2, bf, true);
-    if (need_w1 <= lds_max) {
-      op->use_w1 = true;
-      op->lds = (int)std::max<size_t>((size_t)op->lds, need_w1);
-    }
-  }
+  // the three-pass LDS above was planned for the formed product when tk2 holds
+  op->use_w1 = (op->fmt == TFMM_FMT_TUCKER4D || op->fmt == TFMM_FMT_HTUCKER4D) && !op->fused && op->tk2 &&
+               !op->ctx->no_w1;
   return TFMM_OK;
 }
 

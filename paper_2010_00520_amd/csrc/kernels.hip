@@ -190,11 +190,18 @@ size_t tt4d_chained_lds_bytes(int n3, int r2, bool bf) {
 
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w1) {
   TuckerLds L;
+  if (w1) {
+    if (bf)
+      L.plan_w1<true>(qt / n2, n2, n3, r2);
+    else
+      L.plan_w1<false>(qt / n2, n2, n3, r2);
+    return (size_t)L.total_w1 * sizeof(float2);
+  }
   if (bf)
     L.plan<true>(qt / n2, n2, n3, r1, r2);
   else
     L.plan<false>(qt / n2, n2, n3, r1, r2);
-  return (size_t)(w1 ? L.total_w1 : L.total) * sizeof(float2);
+  return (size_t)L.total * sizeof(float2);
 }
 
 // ---------------------------------------------------------------------------

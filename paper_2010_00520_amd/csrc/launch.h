@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace tfmm {
 
 // Operator family seen by the z-stage kernel.
@@ -53,9 +55,24 @@ size_t zstage_lds_bytes(int fmt, int n1, int n2, int n3, int qt, int KC, int r1,
 // LDS of the three-pass z-stage's y- and z-stages (zstage_planes): the
 // restored tile (64 cb pencils, rows of n3 + 1 complex) and the tile's half
 // spectra of rg RHS at a time (rows of K3 | 1).
+// With n3 <= 32 the tile moves into registers after a pass through LDS and its
+// region is then reused for the half spectra (the larger of the two counts);
+// a 48-point pencil with its transforms needs more than 256 vector registers,
+// so longer pencils keep the tile in LDS.  Kernels whose whole item fits 256
+// registers per lane without spilling (FULL and the restoration from a formed
+// W1 up to n3 = 32, TT-4D up to n3 = 24, TT-3D at n3 = 8) are built for two
+// waves per SIMD; the others for one.
+__host__ __device__ constexpr bool zplanes_tile_in_regs(int T) { return T <= 4; }
+__host__ __device__ constexpr int zplanes_waves_per_simd(int fmt, int T) {
+  return !zplanes_tile_in_regs(T)                           ? 1
+         : (fmt == ZF_FULL || fmt == ZF_TUCKER_W1)          ? 2
+         : (fmt == ZF_TT4D && T <= 3) || (fmt == ZF_TT3D && T <= 1) ? 2
+                                                              : 1;
+}
 inline size_t zplanes_lds_bytes(int n3, int cb, int rg) {
   const size_t qt = (size_t)64 * cb, kp = (size_t)((n3 / 2) | 1);
-  return (qt * (n3 + 1) + (size_t)rg * qt * kp) * 8;
+  const size_t tile = qt * (n3 + 1), half = (size_t)rg * qt * kp;
+  return (zplanes_tile_in_regs(n3 / 8) ? std::max(tile, half) : tile + half) * 8;
 }
 // LDS bytes of the register-chained Tucker restoration of a qt-pencil tile.
 size_t tucker2_lds_bytes(int n2, int n3, int qt, int r1, int r2, bool bf, bool w1 = false);

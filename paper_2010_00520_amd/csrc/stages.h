@@ -508,15 +508,22 @@ __device__ __forceinline__ void yline(bool fwd, int n2, const float2* src, int s
 #undef TFMM_YL
 }
 
+// The restored tile reaches the per-lane pencil layout through LDS (lane l of
+// wave w takes pencil 16 CB w + l, all n3 frequencies).  With n3 <= 32 it is
+// then held in registers (zplanes_tile_in_regs), so the tile's LDS is free for
+// the half spectra (and, where the kernel is built for two waves per SIMD, two
+// blocks share a compute unit); longer pencils keep it in LDS next to the half
+// spectra.
 template <int T, int CB>
 __device__ __forceinline__ void zstage_planes(const v4f (&acc)[T][CB], const ZArgs& a, int pl, int q0,
                                               float2* lds) {
   constexpr int N3 = 8 * T, K = 4 * T, PS = N3 + 1, NPW = 16 * CB, QT = 4 * NPW, KP = K | 1;
+  constexpr bool REG = zplanes_tile_in_regs(T);
   static_assert(NPW <= 64, "one pencil per lane");  // LDS: zplanes_lds_bytes
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, j = l & 15;
   const int n2 = a.n2, K2 = n2 / 2, nf = QT / n2, fx0 = q0 / n2, rg = a.rg;
   float2* reg = lds + w * (NPW * PS);
-  float2* Hl = lds + QT * PS;     // [rg][QT][KP]: half spectra of rg RHS
+  float2* Hl = REG ? lds : lds + QT * PS;  // [rg][QT][KP]: half spectra of rg RHS
   __syncthreads();  // the restoration is done with its LDS
 #pragma unroll
   for (int c = 0; c < CB; ++c)
@@ -525,9 +532,18 @@ __device__ __forceinline__ void zstage_planes(const v4f (&acc)[T][CB], const ZAr
 #pragma unroll
       for (int e = 0; e < 2; ++e)
         reg[(c * 16 + j) * PS + 8 * t + 2 * g + e] = make_float2(acc[t][c][2 * e], acc[t][c][2 * e + 1]);
+  float2 tr[REG ? N3 : 1];
+  if constexpr (REG) {
+    __syncthreads();
+    if (l < NPW) {
+#pragma unroll
+      for (int m = 0; m < N3; ++m) tr[m] = reg[l * PS + m];
+    }
+  }
   const int nline = nf * K;       // (fx, z) lines per RHS
   const long long plane = (long long)K2 * K;
   const float2* tz = reg + l * PS;
+  auto T_at = [&](int m) { return REG ? tr[m] : tz[m]; };
   const float2* wz = a.roots;     // wz[z] = w^z
   for (int s0 = 0; s0 < a.nrhs; s0 += rg) {
     const int nr = min(rg, a.nrhs - s0);
@@ -549,11 +565,11 @@ __device__ __forceinline__ void zstage_planes(const v4f (&acc)[T][CB], const ZAr
 #pragma unroll
         for (int z = 0; z < K; ++z) x[z] = cmul(x[z], wz[z]);
 #pragma unroll
-        for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m]);
+        for (int m = 0; m < K; ++m) E[m] = cmul(E[m], T_at(2 * m));
         DftFull<K>::inv(E, ye);
         DftFull<K>::fwd(x, E);
 #pragma unroll
-        for (int m = 0; m < K; ++m) E[m] = cmul(E[m], tz[2 * m + 1]);
+        for (int m = 0; m < K; ++m) E[m] = cmul(E[m], T_at(2 * m + 1));
         DftFull<K>::inv(E, x);
 #pragma unroll
         for (int z = 0; z < K; ++z) h[z] = cadd(ye[z], cmulconj(x[z], wz[z]));
@@ -627,7 +643,7 @@ __device__ __forceinline__ void zstage_item(const ZArgs& a, int it, float2* lds)
 // items than resident blocks enters the queue loop (a separate copy of the
 // item body, so the common single-item path carries no loop state).
 template <int FMT, int T, int CB, bool BF>
-__global__ __launch_bounds__(256) void k_zstage(ZArgs a) {
+__global__ __launch_bounds__(256, zplanes_waves_per_simd(FMT, T)) void k_zstage(ZArgs a) {
   extern __shared__ float2 lds[];
   constexpr int QT = 16 * CB * 4;
   const int nitems = a.nq / QT * a.ndl;

@@ -123,7 +123,7 @@ __device__ __forceinline__ void stq(float2* row, int k, float2 v) {
 // chunk, C chunk (rows padded to an even number of b), W1 chunk.
 struct TuckerLds {
   int s1, s2, fs, oU1, oU2, oV, oC, oW1, total;
-  int oW1b, total_w1;  // restoration from a formed W1: a second W1 buffer past `total`
+  int oW1b, total_w1;  // restoration from a formed W1 (plan_w1): U2, V and two W1 buffers
   template <bool BF>
   __host__ __device__ __forceinline__ void plan(int nfx, int n2, int n3, int r1, int r2) {
     s1 = tk_stride<BF>(r1);
@@ -137,6 +137,19 @@ struct TuckerLds {
     total = tk_align4(oW1 + nfx * fs);
     oW1b = total;
     total_w1 = tk_align4(oW1b + nfx * fs);
+  }
+  // restoration from a formed W1: no U1 and no core chunk
+  template <bool BF>
+  __host__ __device__ __forceinline__ void plan_w1(int nfx, int n2, int n3, int r2) {
+    s1 = 0;
+    s2 = tk_stride<BF>(r2);
+    fs = 8 * s2 + 2;
+    oU1 = oC = 0;
+    oU2 = 0;
+    oV = tk_align4(oU2 + n2 * s2);
+    oW1 = tk_align4(oV + 8 * n3);
+    oW1b = tk_align4(oW1 + nfx * fs);
+    total = total_w1 = tk_align4(oW1b + nfx * fs);
   }
 };
 
@@ -618,7 +631,7 @@ __device__ __forceinline__ void restore_tucker_w1(v4f (&acc)[T][CB], const ZArgs
   const float2* U3 = a.fbase + d[3];
   const int nfx = QT / n2, fx0 = q0 / n2;
   TuckerLds L;
-  L.plan<BF>(nfx, n2, N3, d[4], r2);
+  L.plan_w1<BF>(nfx, n2, N3, r2);
   const int s2 = L.s2, fs = L.fs, kp2 = tk_kpad<BF>(r2);
   const int ks2 = kp2 / X::KS;
   float2* sU2 = lds + L.oU2;
