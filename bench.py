@@ -87,7 +87,8 @@ def restore_macs(fmt, ranks, n, ndir):
         a2 = ndir * (n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3)
     elif fmt == "htucker4d":
         r1, r2, r3, r4, r12, r34 = ranks[:6]
-        a1 = ndir * (r3 * r4 * r34 + r3 * r34 * r12 + r1 * r2 * r12 * r3)
+        # the root transfer matrix is absorbed into the (3,4) node at upload
+        a1 = ndir * (r3 * r4 * r12 + r1 * r2 * r12 * r3)
         a2 = ndir * (n1 * r1 * r2 * r3 + n1 * n2 * r2 * r3 + N * r3)
     elif fmt == "tt4d":
         r1, r2, r3 = ranks[:3]

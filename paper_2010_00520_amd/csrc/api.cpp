@@ -511,6 +511,30 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
   // compressed: factors as complex64 in the import layout
   std::vector<float2> h(F.data.size());
   for (size_t i = 0; i < h.size(); ++i) h[i] = make_float2((float)F.data[i].real(), (float)F.data[i].imag());
+  if (op->fmt == TFMM_FMT_HTUCKER4D) {
+    // the root transfer matrix B is absorbed into the (3,4) interior node, in
+    // FP64: E[(a3 a4)][b] = sum_b' C34[(a3 a4)][b'] B[b][b'] (r3 r4 x r12) follows
+    // C12 on the device in place of C34 and B (an equivalent tree with an
+    // identity root)
+    const std::vector<int32_t>& rk = F.ranks;
+    const int r1 = rk[0], r2 = rk[1], r3 = rk[2], r4 = rk[3], r12 = rk[4], r34 = rk[5];
+    const size_t oU4 = (size_t)n1 * r1 + (size_t)n2 * r2 + (size_t)n3 * r3, oC12 = oU4 + (size_t)nd * r4,
+                 oC34 = oC12 + (size_t)r1 * r2 * r12, oB = oC34 + (size_t)r3 * r4 * r34;
+    const size_t rows = (size_t)r3 * r4;
+    h.resize(oC34 + rows * r12);
+    std::vector<std::thread> pool;
+    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (int t = 0; t < nt; ++t)
+      pool.emplace_back([&, t] {
+        for (size_t m = t; m < rows; m += nt)
+          for (int b = 0; b < r12; ++b) {
+            cd acc = 0.0;
+            for (int k = 0; k < r34; ++k) acc += F.data[oC34 + m * r34 + k] * F.data[oB + (size_t)b * r34 + k];
+            h[oC34 + m * r12 + b] = make_float2((float)acc.real(), (float)acc.imag());
+          }
+      });
+    for (auto& th : pool) th.join();
+  }
   op->stored_elems = h.size();
   op->desc.assign((size_t)8 * nd, 0);
   const std::vector<int32_t>& r = F.ranks;
@@ -553,7 +577,7 @@ tfmm_status build_device_op(tfmm_ctx c, tfmm_op op) {
       d[4] = r1; d[5] = r2; d[6] = r3;
     }
     a1 = (size_t)nd * r1 * r2 * r3;                                    // per-direction cores
-    if (op->fmt == TFMM_FMT_HTUCKER4D) a1 += (size_t)nd * r3 * (r[4] + r[5]);  // X1, X2
+    if (op->fmt == TFMM_FMT_HTUCKER4D) a1 += (size_t)nd * r3 * r[4];  // X2
     (void)r4;
   } else if (op->fmt == TFMM_FMT_TT4D) {
     const int r2 = r[1];
@@ -758,19 +782,16 @@ tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
     HIP_TRY(tfmm::launch_cgemm(m, nd, r4, 1, GOp{D, r4, 1, 0}, GOp{D + oU4, 1, r4, 0}, scr, 1, m, 0, st));
     L.done();
   } else if (op->fmt == TFMM_FMT_HTUCKER4D) {
-    const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3], r12 = r[4], r34 = r[5];
+    const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3], r12 = r[4];
     const long long oU4 = (long long)n1 * r1 + (long long)n2 * r2 + (long long)n3 * r3;
-    const long long oC12 = oU4 + (long long)nd * r4, oC34 = oC12 + (long long)r1 * r2 * r12,
-                    oB = oC34 + (long long)r3 * r4 * r34;
+    const long long oC12 = oU4 + (long long)nd * r4, oE = oC12 + (long long)r1 * r2 * r12;
     float2* Cp = scr;
-    float2* X1 = Cp + (size_t)nd * r1 * r2 * r3;
-    float2* X2 = X1 + (size_t)nd * r3 * r34;
+    float2* X2 = Cp + (size_t)nd * r1 * r2 * r3;
     Launch L(c, st, "a1_htucker4d");
-    // X1[p][a3][b'] = sum_a4 C34[a3][a4][b'] U4[p][a4]     (Fig. 3(c): C1 times row p of U4)
-    HIP_TRY(tfmm::launch_cgemm(r34, nd, r4, r3, GOp{D + oC34, 1, r34, (long long)r4 * r34}, GOp{D + oU4, 1, r4, 0},
-                               X1, 1, (long long)r3 * r34, r34, st));
-    // X2[p][a3][b] = sum_b' X1[p][a3][b'] B[b][b']            (times the transfer matrix)
-    HIP_TRY(tfmm::launch_cgemm(nd * r3, r12, r34, 1, GOp{X1, r34, 1, 0}, GOp{D + oB, 1, r34, 0}, X2, r12, 1, 0, st));
+    // X2[p][a3][b] = sum_a4 E[a3][a4][b] U4[p][a4]   (Fig. 3(c): the (3,4) node, root
+    // matrix absorbed at upload, times row p of U4)
+    HIP_TRY(tfmm::launch_cgemm(r12, nd, r4, r3, GOp{D + oE, 1, r12, (long long)r4 * r12}, GOp{D + oU4, 1, r4, 0},
+                               X2, 1, (long long)r3 * r12, r12, st));
     // Cp[p][a1 a2][a3] = sum_b C12[a1 a2][b] X2[p][a3][b]     (times C2)
     HIP_TRY(tfmm::launch_cgemm(r1 * r2, r3, r12, nd, GOp{D + oC12, r12, 1, 0}, GOp{X2, 1, r12, (long long)r3 * r12},
                                Cp, r3, 1, (long long)r1 * r2 * r3, st));
