@@ -231,3 +231,51 @@ def test_direction_chunking_invariance(fmt, K):
     assert torch.equal(outs["1"], outs["4096"])
     got = outs["1"].numpy().astype(np.complex128)
     assert O.rel_l2(got, O.translate_compressed(A_np, comp)) < 2e-5
+
+
+@pytest.mark.parametrize("fmt", ["tucker4d", "htucker4d", "tt4d"])
+def test_gemm_tile_measurement_leaves_results_unchanged(fmt):
+    """tfmm_autotune also measures the block tile of each batched GEMM shape the
+    operator runs (a1) and keeps the fastest; the K order of every output is the
+    same for all tiles, so the translation must be bit-for-bit unchanged.  The
+    z-stage plan is pinned (no fused path, LDS-staged restoration, one admissible
+    pencil tile at 24^3 FFT points), so only the GEMM tiles can change."""
+    import paper_2010_00520_amd as P
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    K, L = (12, 12, 12), 3
+    n = tuple(2 * k for k in K)
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(seed=97)
+    # ranks used by no other test: the GEMM shapes have no measured tile yet
+    ranks = {"tucker4d": (11, 9, 13, 23), "htucker4d": (11, 9, 13, 21, 19, 17), "tt4d": (11, 23, 19)}[fmt]
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    env = {"TFMM_NO_FUSED": "1", "TFMM_NO_TK2": "1", "TFMM_GRAPH": "0"}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        ctx = P.Context(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    op = ctx.import_factors(K, L, fmt, rk, data)
+    A_np = synth.gaussian_patterns((2, ndir) + K, 35)
+    A = torch.from_numpy(A_np).cuda()
+    B1, B2 = torch.zeros_like(A), torch.zeros_like(A)
+    ctx.translate(op, A, B1)
+    torch.cuda.synchronize()
+    before = op.plan()
+    ctx.autotune(op, nrhs=2, reps=2)
+    after = op.plan()
+    assert (before["fused"], before["cb"], before["register_chained"]) == \
+        (after["fused"], after["cb"], after["register_chained"]) == (False, 3, False)
+    ctx.translate(op, A, B2)
+    torch.cuda.synchronize()
+    assert torch.equal(B1.cpu(), B2.cpu())
+    assert O.rel_l2(B2.cpu().numpy().astype(np.complex128), O.translate_compressed(A_np, comp)) < 2e-5
+    op.release()
+    ctx.close()
