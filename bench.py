@@ -500,7 +500,8 @@ def bench_precision(args):
                 nr = 6 if fmt == "htucker4d" else 3
                 ranks, data = list(info["ranks"][:nr]), op.export()
                 for prec in ("fp32", "bf16x3"):
-                    o = op if prec == "fp32" else ctx.import_factors(w.K, w.L, fmt, ranks, data, prec=prec)
+                    o = op if prec == "fp32" else ctx.import_factors(w.K, w.L, fmt, ranks, data, prec=prec,
+                                                                     tol=tol)
                     plan, _ = ctx.autotune(o, nrhs=nrhs, reps=10)
                     B = torch.zeros_like(A)
                     ms, lat, kt = time_steps(ctx, o, A, B, args.steps, args.warmup, torch)
@@ -562,7 +563,7 @@ def run_workload(ctx, w, fmt, precs, side, steps, warmup, torch, P, with_B=False
         else:
             # the same factors in the other arithmetic (the compression does not
             # depend on it)
-            op = ctx.import_factors(w.K, w.L, fmt, exported[0], exported[1], prec=prec)
+            op = ctx.import_factors(w.K, w.L, fmt, exported[0], exported[1], prec=prec, tol=w.tol)
         setup_s = time.perf_counter() - t0
         tuned = ctx.autotune(op, nrhs=w.nrhs, reps=5)
         ms, lat, kt = time_steps(ctx, op, A, B, steps, warmup, torch)

@@ -76,11 +76,12 @@ typedef enum {
                               root r12 x r34, Eq. (11), balanced tree {1,2}{3,4}       */
 } tfmm_format;
 
-/* Arithmetic of the per-direction restoration contractions (the FFTs, the
- * pointwise product and the once-per-call contraction of a 4-D core with the
- * direction factor are always FP32).  BF16X3 splits each FP32 operand into a bf16 high
- * part and a bf16 remainder and accumulates hi*hi + hi*lo + lo*hi in FP32 on
- * the matrix cores. */
+/* Arithmetic of the per-direction restoration contractions (the FFTs and the
+ * pointwise product are always FP32).  BF16X3 splits each FP32 operand into a
+ * bf16 high part and a bf16 remainder and accumulates hi*hi + hi*lo + lo*hi in
+ * FP32 on the matrix cores.  The once-per-call GEMMs (the per-direction cores
+ * of the 4-D formats and the formed x-mode / x-y products) use BF16X3 too for
+ * an operator set up by tfmm_setup_compressed at tol >= 1e-5, else FP32. */
 typedef enum { TFMM_PREC_FP32 = 0, TFMM_PREC_BF16X3 = 1 } tfmm_precision;
 
 /* Near-field rule (Section II-A): box pairs closer than the rule are handled
@@ -184,7 +185,9 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx ctx, const tfmm_problem* prob, tfmm_o
 
 /* Build an operator from caller-supplied factors instead of sampling and
  * compressing.  `prob` supplies K, the direction count (n_theta * n_phi, or
- * L-derived), fmt and prec; the physical fields are ignored.  `ranks` and
+ * L-derived), fmt and prec, and optionally in `tol` the tolerance the factors
+ * were compressed at (0: unknown; it only selects the arithmetic of the
+ * once-per-call GEMMs, see tfmm_precision); the physical fields are ignored.  `ranks` and
  * `data` (complex128, host memory, caller-owned, read during the call only)
  * are laid out as follows, all arrays C order:
  *   FULL      ranks: none (nranks 0);  data: T~[n_dir][n1][n2][n3]

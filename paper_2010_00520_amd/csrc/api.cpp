@@ -97,6 +97,7 @@ struct tfmm_op_s {
   // direction's core is formed by a batched GEMM per direction chunk, and the
   // z-stage restores from it (ZF_TUCKER_W1)
   bool use_w1 = false;
+  double tol = 0.0;                    // compression tolerance of tfmm_setup_compressed (0: imported)
   // TT-3D on the three-pass path with register-chained restoration: the x-y
   // products W_p[q][b] = sum_a U1_p[fx][a] C_p[a][fy][b] of every direction are
   // formed by one batched GEMM per call (wtt_elems complex64 of scratch)
@@ -769,17 +770,25 @@ struct Launch {
   }
 };
 
+// The per-call GEMMs (a1 and the formed products) of an operator restored in
+// bf16x3 run in the same split arithmetic when it was compressed at gamma >=
+// 1e-5: their rounding (a few 1e-6 relative) then stays an order below the
+// compression error.  At smaller gamma, and for imported factors (no gamma),
+// they run in FP32.
+static bool gemm_bf16x3(const tfmm_op_s* op) { return op->prec == TFMM_PREC_BF16X3 && op->tol >= 1e-5; }
+
 tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
   using tfmm::GOp;
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], nd = op->ndir;
   const auto& r = op->host.ranks;
   const float2* D = op->d_data;
+  const bool bfg = gemm_bf16x3(op);
   if (op->fmt == TFMM_FMT_TUCKER4D) {
     const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3];
     const int m = r1 * r2 * r3;
     const long long oU4 = (long long)m * r4 + (long long)n1 * r1 + (long long)n2 * r2 + (long long)n3 * r3;
     Launch L(c, st, "a1_tucker4d");
-    HIP_TRY(tfmm::launch_cgemm(m, nd, r4, 1, GOp{D, r4, 1, 0}, GOp{D + oU4, 1, r4, 0}, scr, 1, m, 0, st));
+    HIP_TRY(tfmm::launch_cgemm(m, nd, r4, 1, GOp{D, r4, 1, 0}, GOp{D + oU4, 1, r4, 0}, scr, 1, m, 0, st, bfg));
     L.done();
   } else if (op->fmt == TFMM_FMT_HTUCKER4D) {
     const int r1 = r[0], r2 = r[1], r3 = r[2], r4 = r[3], r12 = r[4];
@@ -791,10 +800,10 @@ tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
     // X2[p][a3][b] = sum_a4 E[a3][a4][b] U4[p][a4]   (Fig. 3(c): the (3,4) node, root
     // matrix absorbed at upload, times row p of U4)
     HIP_TRY(tfmm::launch_cgemm(r12, nd, r4, r3, GOp{D + oE, 1, r12, (long long)r4 * r12}, GOp{D + oU4, 1, r4, 0},
-                               X2, 1, (long long)r3 * r12, r12, st));
+                               X2, 1, (long long)r3 * r12, r12, st, bfg));
     // Cp[p][a1 a2][a3] = sum_b C12[a1 a2][b] X2[p][a3][b]     (times C2)
     HIP_TRY(tfmm::launch_cgemm(r1 * r2, r3, r12, nd, GOp{D + oC12, r12, 1, 0}, GOp{X2, 1, r12, (long long)r3 * r12},
-                               Cp, r3, 1, (long long)r1 * r2 * r3, st));
+                               Cp, r3, 1, (long long)r1 * r2 * r3, st, bfg));
     L.done();
   } else if (op->fmt == TFMM_FMT_TT4D) {
     const int r1 = r[0], r2 = r[1], r3 = r[2];
@@ -805,11 +814,11 @@ tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
     Launch L(c, st, "a1_tt4d");
     // T1[(x,y)][b] = sum_a U1[x][a] C1[a][y][b]               (Fig. 4(a) step 1, shared by all p)
     HIP_TRY(tfmm::launch_cgemm(n1, r2, r1, n2, GOp{D, r1, 1, 0}, GOp{D + oC1, (long long)n2 * r2, 1, r2}, T1,
-                               (long long)n2 * r2, 1, r2, st));
+                               (long long)n2 * r2, 1, r2, st, bfg));
     // V[p][z][b] = sum_c C2[b][z][c] U3[p][c]                  (Fig. 4(b) step 1, column p)
     // one GEMM per z (rows b, columns p), so each output column is a contiguous run of b
     HIP_TRY(tfmm::launch_cgemm(r2, nd, r3, n3, GOp{D + oC2, (long long)n3 * r3, 1, r3}, GOp{D + oU3, 1, r3, 0}, V,
-                               1, (long long)n3 * r2, r2, st));
+                               1, (long long)n3 * r2, r2, st, bfg));
     L.done();
   }
   return TFMM_OK;
@@ -845,7 +854,7 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
     int r2max = 1;
     for (int p = 0; p < nd; ++p) r2max = std::max(r2max, op->desc[8 * p + 5]);
     Launch L(c, st, "a1_tt3d_w");
-    HIP_TRY(tfmm::launch_cgemm_tt3d(n1, n2, n2 * r2max, nd, op->d_desc, op->d_data, W1, st));
+    HIP_TRY(tfmm::launch_cgemm_tt3d(n1, n2, n2 * r2max, nd, op->d_desc, op->d_data, W1, gemm_bf16x3(op), st));
     L.done();
   }
   float2* roots = op->d_roots_z;
@@ -923,7 +932,8 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
         const long long m = (long long)r1 * r2 * r3, r23 = (long long)r2 * r3;
         Launch L(c, st, "a1_w1");
         HIP_TRY(tfmm::launch_cgemm(n1, (int)r23, r1, nl, tfmm::GOp{op->d_data + op->desc[1], r1, 1, 0},
-                                   tfmm::GOp{a1 + (size_t)p0 * m, r23, 1, m}, W1, r23, 1, z.w1dir, st));
+                                   tfmm::GOp{a1 + (size_t)p0 * m, r23, 1, m}, W1, r23, 1, z.w1dir, st,
+                                   gemm_bf16x3(op)));
         L.done();
       }
       z.p0 = p0;
@@ -1431,6 +1441,7 @@ tfmm_status tfmm_setup_compressed(tfmm_ctx c, const tfmm_problem* P, tfmm_op* ou
   // compression (Algorithms 1-3): the 4-D formats on the device, the
   // per-direction 3-D formats on the host
   tfmm_op op = new_op(c, P, ndir, L);
+  op->tol = P->fmt == TFMM_FMT_FULL ? 0.0 : P->tol;
   const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   const bool four_d = P->fmt == TFMM_FMT_TUCKER4D || P->fmt == TFMM_FMT_TT4D || P->fmt == TFMM_FMT_HTUCKER4D;
   if (four_d && !c->host_compress) {
@@ -1502,6 +1513,7 @@ tfmm_status tfmm_op_import(tfmm_ctx c, const tfmm_problem* P, const int32_t* ran
   std::lock_guard<std::recursive_mutex> g(c->mu);
   HIP_TRY(hipSetDevice(c->device));
   tfmm_op op = new_op(c, P, ndir, L);
+  op->tol = P->fmt == TFMM_FMT_FULL || !(P->tol > 0 && P->tol < 1) ? 0.0 : P->tol;
   op->host.fmt = (int)P->fmt;
   for (int i = 0; i < 3; ++i) op->host.n[i] = n[i];
   op->host.ndir = ndir;

@@ -365,13 +365,162 @@ __global__ __launch_bounds__(256) void k_cgemm(int M, int N_, int K_, GOp A_, GO
     }
 }
 
+// Split-BF16 variant (operators restored in bf16x3): operands are split into
+// bf16 hi/lo once as they are staged, each 16x16x32 bf16 step takes 16
+// complex k as hi.hi + hi.lo + lo.hi with FP32 accumulation (the arithmetic
+// of the bf16x3 restoration), on a chunk of KC = 32 complex k.  LDS holds A as
+// rows m and B as rows n, both k-contiguous (uint2 hi/lo per complex), so a
+// lane's four k of a fragment are two 16-byte loads; rows are padded by four
+// complex against bank conflicts.
 template <int TM, int TN, int WGM, int WGN, bool DESC, bool DB>
+__global__ __launch_bounds__(256) void k_cgemm_bf(int M, int N_, int K_, GOp A_, GOp B_, float2* __restrict__ C_,
+                                                  long long cs0_, long long cs1_, long long csb_, int tiles_n,
+                                                  GDesc G) {
+  static_assert(WGM * WGN == 4, "four waves per block");
+  constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN, KC = 32, RS = KC + 4;
+  constexpr int EA = BM * KC / 256, EB = KC * BN / 256;
+  static_assert(EA * 256 == BM * KC && EB * 256 == KC * BN, "whole tiles per thread");
+  __shared__ uint2 sA[(DB ? 2 : 1) * BM * RS];
+  __shared__ uint2 sB[(DB ? 2 : 1) * BN * RS];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int tmb = blockIdx.x / tiles_n, tnb = blockIdx.x - tmb * tiles_n;
+  const int m0 = tmb * BM, n0 = tnb * BN;
+  int N = N_, K = K_;
+  GOp A = A_, B = B_;
+  float2* C = C_;
+  long long cs0 = cs0_, cs1 = cs1_, csb = csb_;
+  if constexpr (DESC) {
+    const int* d = G.desc + 8 * blockIdx.y;
+    K = d[4];
+    N = G.n2 * d[5];
+    if (n0 >= N) return;
+    A = GOp{G.fbase + d[1], K, 1, 0};
+    B = GOp{G.fbase + d[0], N, 1, 0};
+    C = G.wout + d[7];
+    cs0 = N;
+    cs1 = 1;
+    csb = 0;
+  }
+  const float2* __restrict__ Ap = A.p + (long long)blockIdx.y * A.sb;
+  const float2* __restrict__ Bp = B.p + (long long)blockIdx.y * B.sb;
+  const bool akf = A.s1 == 1, bkf = B.s0 == 1;
+  float2 ra[EA], rb[EB];
+  auto a_pos = [&](int e, int& mm, int& kk) {
+    if (akf) { kk = e % KC; mm = e / KC; } else { mm = e % BM; kk = e / BM; }
+  };
+  auto b_pos = [&](int e, int& kk, int& nn) {
+    if (bkf) { kk = e % KC; nn = e / KC; } else { nn = e % BN; kk = e / BN; }
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      int mm, kk;
+      a_pos(tid + 256 * u, mm, kk);
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[u] = (gm < M && gk < K) ? Ap[(long long)gm * A.s0 + (long long)gk * A.s1] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      int kk, nn;
+      b_pos(tid + 256 * u, kk, nn);
+      const int gk = k0 + kk, gn = n0 + nn;
+      rb[u] = (gk < K && gn < N) ? Bp[(long long)gk * B.s0 + (long long)gn * B.s1] : make_float2(0.f, 0.f);
+    }
+  };
+  auto store = [&](int buf) {
+    uint2* dA = sA + buf * (BM * RS);
+    uint2* dB = sB + buf * (BN * RS);
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      int mm, kk;
+      a_pos(tid + 256 * u, mm, kk);
+      dA[mm * RS + kk] = split_bf3(ra[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      int kk, nn;
+      b_pos(tid + 256 * u, kk, nn);
+      dB[nn * RS + kk] = split_bf3(rb[u]);
+    }
+  };
+  const int wm = w / WGN, wn = w - wm * WGN;
+  const int i = l & 15, kg = l >> 4, ri = i & 1, g = kg;
+  v4f acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  auto chunk = [&](const uint2* cA, const uint2* cB) {
+#pragma unroll
+    for (int s = 0; s < KC / 16; ++s) {
+      v4u ahi[TM], alo[TM], bhi[TN], blo[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) {
+        const uint4* p = reinterpret_cast<const uint4*>(cA + ((wm * TM + a) * 8 + (i >> 1)) * RS + 16 * s + 4 * kg);
+        const uint4 x = p[0], y = p[1];
+        ahi[a] = v4u{embed_a_bf(x.x, ri), embed_a_bf(x.z, ri), embed_a_bf(y.x, ri), embed_a_bf(y.z, ri)};
+        alo[a] = v4u{embed_a_bf(x.y, ri), embed_a_bf(x.w, ri), embed_a_bf(y.y, ri), embed_a_bf(y.w, ri)};
+      }
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        const uint4* p = reinterpret_cast<const uint4*>(cB + ((wn * TN + b) * 16 + i) * RS + 16 * s + 4 * kg);
+        const uint4 x = p[0], y = p[1];
+        bhi[b] = v4u{x.x, x.z, y.x, y.z};
+        blo[b] = v4u{x.y, x.w, y.y, y.w};
+      }
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = mfma_bf3(ahi[a], alo[a], bhi[b], blo[b], acc[a][b]);
+    }
+  };
+  const int nk = (K + KC - 1) / KC;
+  load(0);
+  if constexpr (DB) {
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nk; ++c) {
+      const int cur = c & 1;
+      if (c + 1 < nk) load((c + 1) * KC);
+      chunk(sA + cur * (BM * RS), sB + cur * (BN * RS));
+      if (c + 1 < nk) store(cur ^ 1);
+      __syncthreads();
+    }
+  } else {
+    for (int c = 0; c < nk; ++c) {
+      __syncthreads();
+      store(0);
+      __syncthreads();
+      if (c + 1 < nk) load((c + 1) * KC);
+      chunk(sA, sB);
+    }
+  }
+  float2* Cb = C + (long long)blockIdx.y * csb;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int cn = n0 + (wn * TN + b) * 16 + i, cm0 = m0 + (wm * TM + a) * 8 + 2 * g;
+      if (cn < N) {
+        float2* cp = Cb + (long long)cn * cs1;
+        if (cm0 < M) cp[(long long)cm0 * cs0] = make_float2(acc[a][b][0], acc[a][b][1]);
+        if (cm0 + 1 < M) cp[(long long)(cm0 + 1) * cs0] = make_float2(acc[a][b][2], acc[a][b][3]);
+      }
+    }
+}
+
+template <int TM, int TN, int WGM, int WGN, bool DESC, bool DB, bool BF>
 static hipError_t run_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                             long long csb, hipStream_t st, GDesc G) {
   constexpr int BM = 8 * TM * WGM, BN = 16 * TN * WGN;
   const int tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
-  hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN, DESC, DB>), dim3((unsigned)(tiles_m * tiles_n), (unsigned)nb),
-                     dim3(256), 0, st, M, N, K, A, B, C, cs0, cs1, csb, tiles_n, G);
+  const dim3 grid((unsigned)(tiles_m * tiles_n), (unsigned)nb);
+  if constexpr (BF)
+    hipLaunchKernelGGL((k_cgemm_bf<TM, TN, WGM, WGN, DESC, DB>), grid, dim3(256), 0, st, M, N, K, A, B, C, cs0, cs1,
+                       csb, tiles_n, G);
+  else
+    hipLaunchKernelGGL((k_cgemm<TM, TN, WGM, WGN, DESC, DB>), grid, dim3(256), 0, st, M, N, K, A, B, C, cs0, cs1,
+                       csb, tiles_n, G);
   return hipGetLastError();
 }
 
@@ -405,26 +554,26 @@ static int pick_tile(int M, int N, int nb) {
   return best;
 }
 
-template <bool DESC, bool DB>
+template <bool DESC, bool DB, bool BF>
 static hipError_t run_cgemm_tile(int t, int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0,
                                  long long cs1, long long csb, hipStream_t st, GDesc G) {
   switch (t) {
-    case 0: return run_cgemm<4, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 64 x 64
-    case 1: return run_cgemm<3, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 48 x 64
-    case 2: return run_cgemm<2, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 32 x 64
-    case 3: return run_cgemm<2, 1, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 32 x 32
-    case 4: return run_cgemm<4, 1, 4, 1, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 128 x 16
-    case 5: return run_cgemm<2, 2, 1, 4, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 16 x 128
-    default: return run_cgemm<1, 2, 2, 2, DESC, DB>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);  // 16 x 64
+    case 0: return run_cgemm<4, 2, 2, 2, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 64 x 64
+    case 1: return run_cgemm<3, 2, 2, 2, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 48 x 64
+    case 2: return run_cgemm<2, 2, 2, 2, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 32 x 64
+    case 3: return run_cgemm<2, 1, 2, 2, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 32 x 32
+    case 4: return run_cgemm<4, 1, 4, 1, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 128 x 16
+    case 5: return run_cgemm<2, 2, 1, 4, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);   // 16 x 128
+    default: return run_cgemm<1, 2, 2, 2, DESC, DB, BF>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);  // 16 x 64
   }
 }
 
 // measured configuration per GEMM shape: index = tile * 2 + (two buffers)
 struct GemmKey {
   int M, N, K, nb;
-  bool akf, bkf, desc;
+  bool akf, bkf, desc, bf;
   bool operator<(const GemmKey& o) const {
-    return std::tie(M, N, K, nb, akf, bkf, desc) < std::tie(o.M, o.N, o.K, o.nb, o.akf, o.bkf, o.desc);
+    return std::tie(M, N, K, nb, akf, bkf, desc, bf) < std::tie(o.M, o.N, o.K, o.nb, o.akf, o.bkf, o.desc, o.bf);
   }
 };
 static std::mutex g_gemm_mu;
@@ -433,15 +582,15 @@ static thread_local bool g_gemm_tuning = false;
 
 void set_gemm_tuning(bool on) { g_gemm_tuning = on; }
 
-template <bool DESC>
+template <bool DESC, bool BF>
 static hipError_t run_cgemm_pick(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
                                  long long csb, hipStream_t st, GDesc G) {
   auto launch = [&](int cfg) {
-    return (cfg & 1) ? run_cgemm_tile<DESC, true>(cfg >> 1, M, N, K, nb, A, B, C, cs0, cs1, csb, st, G)
-                     : run_cgemm_tile<DESC, false>(cfg >> 1, M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);
+    return (cfg & 1) ? run_cgemm_tile<DESC, true, BF>(cfg >> 1, M, N, K, nb, A, B, C, cs0, cs1, csb, st, G)
+                     : run_cgemm_tile<DESC, false, BF>(cfg >> 1, M, N, K, nb, A, B, C, cs0, cs1, csb, st, G);
   };
   // DESC: K per batch comes from the descriptor; the key uses the bound N and no K
-  const GemmKey key{M, N, DESC ? 0 : K, nb, A.s1 == 1, B.s0 == 1, DESC};
+  const GemmKey key{M, N, DESC ? 0 : K, nb, A.s1 == 1, B.s0 == 1, DESC, BF};
   int cfg = -1;
   {
     std::lock_guard<std::mutex> g(g_gemm_mu);
@@ -475,24 +624,27 @@ static hipError_t run_cgemm_pick(int M, int N, int K, int nb, GOp A, GOp B, floa
       g_gemm_pick[key] = cfg;
     }
   }
-  if (cfg < 0) cfg = pick_tile(M, N, nb) * 2 + (K > 32 ? 1 : 0);
+  if (cfg < 0) cfg = pick_tile(M, N, nb) * 2 + (K > (BF ? 64 : 32) ? 1 : 0);
   return launch(cfg);
 }
 
 hipError_t launch_cgemm_tt3d(int n1, int n2, int nmax, int nd, const int* desc, const float2* fbase, float2* wout,
-                             hipStream_t st) {
+                             bool bf, hipStream_t st) {
   if (n1 <= 0 || nmax <= 0 || nd <= 0) return hipSuccess;
   if (nd > 65535) return hipErrorInvalidValue;
   const GDesc G{desc, fbase, wout, n2};
   const GOp none{nullptr, 0, 0, 0};
-  return run_cgemm_pick<true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
+  return bf ? run_cgemm_pick<true, true>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G)
+            : run_cgemm_pick<true, false>(n1, nmax, 0, nd, none, none, nullptr, 0, 0, 0, st, G);
 }
 
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
-                        long long csb, hipStream_t st) {
+                        long long csb, hipStream_t st, bool bf) {
   if (M <= 0 || N <= 0 || nb <= 0) return hipSuccess;
   if (nb > 65535) return hipErrorInvalidValue;
-  return run_cgemm_pick<false>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, GDesc{nullptr, nullptr, nullptr, 0});
+  const GDesc none{nullptr, nullptr, nullptr, 0};
+  return bf ? run_cgemm_pick<false, true>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, none)
+            : run_cgemm_pick<false, false>(M, N, K, nb, A, B, C, cs0, cs1, csb, st, none);
 }
 
 }  // namespace tfmm

@@ -118,8 +118,10 @@ struct GOp {
   const float2* p;
   long long s0, s1, sb;
 };
+// bf: split-BF16 products (bf16x3, FP32 accumulation), for operators restored
+// in that arithmetic; otherwise FP32 MFMA.
 hipError_t launch_cgemm(int M, int N, int K, int nb, GOp A, GOp B, float2* C, long long cs0, long long cs1,
-                        long long csb, hipStream_t st);
+                        long long csb, hipStream_t st, bool bf = false);
 // While on (per thread), a GEMM shape without a measured tile configuration
 // times them all on its stream and keeps the fastest (tfmm_autotune).
 void set_gemm_tuning(bool on);
@@ -127,7 +129,7 @@ void set_gemm_tuning(bool on);
 // (q = fx n2 + fy; per-direction ranks from desc[8p + 4], desc[8p + 5]; W_p at
 // wout + desc[8p + 7]); nmax = n2 * max r2.
 hipError_t launch_cgemm_tt3d(int n1, int n2, int nmax, int nd, const int* desc, const float2* fbase, float2* wout,
-                             hipStream_t st);
+                             bool bf, hipStream_t st);
 
 // FP64 operator sampling, Eq. (7): T[p][m1][m2][m3] (double2) for every direction,
 // wavenumber k = kre + i kim.

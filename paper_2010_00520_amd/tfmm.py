@@ -313,8 +313,9 @@ class Context:
         return Operator(self, h.value)
 
     def import_factors(self, K, L, fmt: str, ranks: Sequence[int], data: np.ndarray, prec="fp32", n_theta=0,
-                       n_phi=0, n_dir=0) -> Operator:
-        prob = make_problem(K, L=L, fmt=fmt, prec=prec, n_theta=n_theta, n_phi=n_phi, n_dir=n_dir)
+                       n_phi=0, n_dir=0, tol=0.0) -> Operator:
+        """tfmm_op_import; `tol`: the tolerance the factors were compressed at (0: unknown)."""
+        prob = make_problem(K, L=L, fmt=fmt, prec=prec, n_theta=n_theta, n_phi=n_phi, n_dir=n_dir, tol=tol)
         r = np.ascontiguousarray(np.asarray(ranks, dtype=np.int32).ravel())
         d = np.ascontiguousarray(np.asarray(data, dtype=np.complex128).ravel()).view(np.float64)
         h = ctypes.c_void_p()

@@ -410,3 +410,27 @@ def test_formed_x_mode_product_restoration(fmt, K, prec):
                 assert O.rel_l2(got[s, p], ref[s, p]) < 5 * tol
         op.release()
         c.close()
+
+
+@pytest.mark.parametrize("fmt", ["tucker4d", "htucker4d", "tt4d", "tt3d"])
+def test_bf16x3_per_call_gemms(ctx, fmt):
+    """An operator restored in bf16x3 whose factors were compressed at tol >=
+    1e-5 forms its per-call GEMMs (4-D cores, formed products) in bf16x3 too;
+    imported without a tolerance it keeps them in FP32.  Both within the bf16x3
+    arithmetic tolerance of the oracle, and not the same bits (a non-cubic
+    grid: the three-pass path, where TT-3D forms its x-y products)."""
+    K, L = (24, 12, 12), 3
+    n = tuple(2 * k for k in K)
+    ndir = (L + 1) * 2 * (L + 1)
+    rng = np.random.default_rng(seed_of("bfgemm", fmt))
+    ranks = {"tucker4d": (9, 11, 13, 17), "htucker4d": (10, 9, 13, 15, 12, 11), "tt4d": (9, 15, 13)}.get(fmt)
+    rk, data, comp = random_factors(fmt, n, ndir, rng, ranks)
+    A = synth.gaussian_patterns((2, ndir) + K, seed_of("bfgemmA", fmt))
+    ref = O.translate_compressed(A, comp)
+    got = {}
+    for tol in (0.0, 1e-4):
+        op = ctx.import_factors(K, L, fmt, rk, data, prec="bf16x3", tol=tol)
+        got[tol] = gpu_translate(ctx, op, A)
+        assert O.rel_l2(got[tol], ref) < 1e-4, (tol, O.rel_l2(got[tol], ref))
+        op.release()
+    assert not np.array_equal(got[0.0], got[1e-4])
