@@ -234,7 +234,12 @@ tfmm_status tfmm_op_release(tfmm_ctx ctx, tfmm_op op);
  * TFMM_GRAPH); at most four graphs are kept per operator, and a graph is
  * dropped when the scratch it uses moves.  The kernels are persistent: they
  * take (direction, pencil tile) work items from a device counter, costliest
- * directions first, so results do not depend on the launch shape. */
+ * directions first, so results do not depend on the launch shape.  On the
+ * three-pass path the per-call GEMMs (the 4-D formats' direction cores and
+ * formed products, TT-3D's formed products) run on an internal stream forked
+ * from `hip_stream` and joined back into it before the first z-stage, beside
+ * the first x pass; everything the call enqueues has finished when
+ * `hip_stream` reaches the end of its work. */
 tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int32_t nrhs,
                            void* hip_stream);
 

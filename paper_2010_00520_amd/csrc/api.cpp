@@ -189,6 +189,13 @@ struct tfmm_ctx_s {
   // is freed only once its own work is done (no device-wide synchronisation)
   hipEvent_t slot_ev[kSlots] = {nullptr, nullptr, nullptr};
   bool slot_ev_set[kSlots] = {false, false, false};
+  // per slot, a second stream for the per-call GEMMs (a1 and the formed
+  // products), which depend on the operator only: forked from the slot's
+  // stream at the start of a translation and joined before the first z-stage,
+  // so they run beside the first x pass, which depends on A only
+  hipStream_t side[kSlots] = {nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev[kSlots] = {nullptr, nullptr, nullptr};
+  hipEvent_t join_ev[kSlots] = {nullptr, nullptr, nullptr};
   int* counters = nullptr;             // device work counters of the persistent launches, one per slot
   int ncu = 0;                         // compute units
   hipStream_t cap_stream = nullptr;    // stream used only for graph capture
@@ -826,10 +833,13 @@ tfmm_status run_a1(tfmm_ctx c, tfmm_op op, float2* scr, hipStream_t st) {
 
 // Enqueue the translation of `nr` right-hand sides (pointer tables) on `st`
 // with the scratch `scr` laid out by `sp`; `counter` = two ints of the
-// persistent launches, zero on entry and left zero.
+// persistent launches, zero on entry and left zero.  With side_slot >= 0 the
+// per-call GEMMs go to that slot's side stream, forked from `st` here and
+// joined back into `st` before the first z-stage (all later work, and the
+// caller's completion event, stay on `st`).
 tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2*>& As,
                               const std::vector<float2*>& Bs, hipStream_t st, void* scr, const ScratchPlan& sp,
-                              int* counter, bool prof) {
+                              int* counter, bool prof, int side_slot) {
   const int n1 = op->n[0], n2 = op->n[1], n3 = op->n[2], K3 = op->K[2], nd = op->ndir;
   const int nr_total = (int)As.size();
   const int rhs_group = sp.rhs_group, ndl = sp.ndl;
@@ -844,17 +854,37 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
     bool v;
     ~Restore() { c->prof = v; }
   } restore{c, prof0};
-  if (op->a1_bytes) {
-    tfmm_status s = run_a1(c, op, a1, st);
-    if (s != TFMM_OK) return s;
-  }
   const bool tt3d_w = op->zfmt == tfmm::ZF_TT3D && op->tk2 && !op->fused;
+  const bool w1_formed = op->use_w1 && !op->fused;
+  // per-call GEMMs beside the first x pass (three-pass path only: the fused
+  // kernel reads A itself)
+  const bool split = side_slot >= 0 && !op->fused && (op->a1_bytes > 0 || tt3d_w || w1_formed);
+  hipStream_t gs = st;
+  if (split) {
+    gs = c->side[side_slot];
+    HIP_TRY(hipEventRecord(c->fork_ev[side_slot], st));
+    HIP_TRY(hipStreamWaitEvent(gs, c->fork_ev[side_slot], 0));
+  }
+  bool joined = !split;
+  auto join = [&]() -> hipError_t {
+    if (joined) return hipSuccess;
+    joined = true;
+    hipError_t e = hipEventRecord(c->join_ev[side_slot], gs);
+    return e == hipSuccess ? hipStreamWaitEvent(st, c->join_ev[side_slot], 0) : e;
+  };
+  if (op->a1_bytes) {
+    tfmm_status s = run_a1(c, op, a1, gs);
+    if (s != TFMM_OK) {
+      (void)join();
+      return s;
+    }
+  }
   if (tt3d_w) {
     // W_p[q][b] = sum_a U1_p[fx][a] C_p[a][fy][b] for every direction (Fig. 4(a) step 1)
     int r2max = 1;
     for (int p = 0; p < nd; ++p) r2max = std::max(r2max, op->desc[8 * p + 5]);
-    Launch L(c, st, "a1_tt3d_w");
-    HIP_TRY(tfmm::launch_cgemm_tt3d(n1, n2, n2 * r2max, nd, op->d_desc, op->d_data, W1, gemm_bf16x3(op), st));
+    Launch L(c, gs, "a1_tt3d_w");
+    HIP_TRY(tfmm::launch_cgemm_tt3d(n1, n2, n2 * r2max, nd, op->d_desc, op->d_data, W1, gemm_bf16x3(op), gs));
     L.done();
   }
   float2* roots = op->d_roots_z;
@@ -926,16 +956,20 @@ tfmm_status enqueue_translate(tfmm_ctx c, tfmm_op op, const std::vector<const fl
       if (z.fmt == tfmm::ZF_TUCKER_W1) {
         // W1[p][fx][b][c] = sum_a U1[fx][a] C_p[a][b][c] for the chunk's directions
         // (Fig. 3(a) step 1, the x-mode product, ahead of the z-stage); C_p is the
-        // per-direction core a1 formed, [p][a][b][c]
+        // per-direction core a1 formed, [p][a][b][c].  The first chunk's runs on
+        // the side stream (nothing has read W1 yet); later chunks' follow the
+        // previous z-stage on `st`.
         const auto& r = op->host.ranks;
         const int r1 = r[0], r2 = r[1], r3 = r[2];
         const long long m = (long long)r1 * r2 * r3, r23 = (long long)r2 * r3;
-        Launch L(c, st, "a1_w1");
+        hipStream_t ws = joined ? st : gs;
+        Launch L(c, ws, "a1_w1");
         HIP_TRY(tfmm::launch_cgemm(n1, (int)r23, r1, nl, tfmm::GOp{op->d_data + op->desc[1], r1, 1, 0},
-                                   tfmm::GOp{a1 + (size_t)p0 * m, r23, 1, m}, W1, r23, 1, z.w1dir, st,
+                                   tfmm::GOp{a1 + (size_t)p0 * m, r23, 1, m}, W1, r23, 1, z.w1dir, ws,
                                    gemm_bf16x3(op)));
         L.done();
       }
+      HIP_TRY(join());
       z.p0 = p0;
       z.nrhs = nr;
       z.ndl = nl;
@@ -972,7 +1006,7 @@ tfmm_status run_translate(tfmm_ctx c, tfmm_op op, const std::vector<const float2
     while (scratch_plan(op, (int)As.size(), cap).ndl > want && cap > 1) cap /= 2;
     sp = scratch_plan(op, (int)As.size(), cap);
   }
-  return enqueue_translate(c, op, As, Bs, st, scr, sp, c->counters + 2 * slot, true);
+  return enqueue_translate(c, op, As, Bs, st, scr, sp, c->counters + 2 * slot, true, slot);
 }
 
 // ---------------------------------------------------------------------------
@@ -1340,6 +1374,13 @@ tfmm_status tfmm_ctx_create(int device, size_t budget, tfmm_ctx* out) {
       delete c;
       return fail(TFMM_ERR_HIP, "event creation failed");
     }
+  for (int i = 0; i < tfmm_ctx_s::kSlots; ++i)
+    if (hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork_ev[i], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming) != hipSuccess) {
+      delete c;
+      return fail(TFMM_ERR_HIP, "side stream creation failed");
+    }
   c->worker = std::thread(worker_loop, c);
   c->completer = std::thread(completer_loop, c);
   *out = c;
@@ -1378,6 +1419,11 @@ tfmm_status tfmm_ctx_destroy(tfmm_ctx c) {
     if (s.ptr) (void)hipFree(s.ptr);
   for (auto& s : c->streams) (void)hipStreamDestroy(s);
   for (auto& e : c->slot_ev) (void)hipEventDestroy(e);
+  for (int i = 0; i < tfmm_ctx_s::kSlots; ++i) {
+    (void)hipStreamDestroy(c->side[i]);
+    (void)hipEventDestroy(c->fork_ev[i]);
+    (void)hipEventDestroy(c->join_ev[i]);
+  }
   (void)hipStreamDestroy(c->cap_stream);
   (void)hipFree(c->counters);
   delete c;
@@ -1679,7 +1725,7 @@ tfmm_status tfmm_translate_noalloc(tfmm_ctx c, tfmm_op op, const void* A, void* 
     As[i] = (const float2*)A + i * blk;
     Bs[i] = (float2*)B + i * blk;
   }
-  return enqueue_translate(c, op, As, Bs, st, base + tfmm::kNoAllocCounterBytes, sp, counter, false);
+  return enqueue_translate(c, op, As, Bs, st, base + tfmm::kNoAllocCounterBytes, sp, counter, false, -1);
 }
 
 // ---------------------------------------------------------------------------
