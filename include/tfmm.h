@@ -254,8 +254,9 @@ tfmm_status tfmm_translate(tfmm_ctx ctx, tfmm_op op, const void* A, void* B, int
  * scratch taken from a fixed device array of TFMM_NOALLOC_SCRATCH_BYTES that
  * the library holds on each device it runs on until the process ends (its
  * address is looked up at context creation).  The call makes no hipMalloc or
- * hipFree and no allocating library call, and never captures or replays a
- * graph (so it may itself be captured).  The direction chunk of the three-pass
+ * hipFree and no allocating library call, never captures or replays a graph
+ * (so it may itself be captured), and enqueues all of its work on
+ * `hip_stream` (no internal stream).  The direction chunk of the three-pass
  * pipeline shrinks until the scratch fits; a translation that does not fit
  * even with one direction per chunk (the per-direction cores of a 4-D format
  * plus one direction's x-FFT'ed planes for all RHS) fails

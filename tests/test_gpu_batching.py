@@ -51,7 +51,7 @@ def _factors(fmt, K, L):
     n = tuple(2 * k for k in K)
     ndir = (L + 1) * 2 * (L + 1)
     rng = np.random.default_rng(4321)
-    ranks = {"htucker4d": (6, 5, 4, 7, 10, 9), "tt4d": (5, 6, 7)}.get(fmt)
+    ranks = {"htucker4d": (6, 5, 4, 7, 10, 9), "tt4d": (5, 6, 7), "tucker4d": (6, 5, 4, 7)}.get(fmt)
     return ndir, random_factors(fmt, n, ndir, rng, ranks)
 
 
@@ -277,5 +277,42 @@ def test_gemm_tile_measurement_leaves_results_unchanged(fmt):
     torch.cuda.synchronize()
     assert torch.equal(B1.cpu(), B2.cpu())
     assert O.rel_l2(B2.cpu().numpy().astype(np.complex128), O.translate_compressed(A_np, comp)) < 2e-5
+    op.release()
+    ctx.close()
+
+
+@pytest.mark.parametrize("fmt,K", [("tucker4d", (12, 8, 8)), ("htucker4d", (24, 8, 8)), ("tt4d", (16, 8, 8)),
+                                   ("tt3d", (8, 12, 4))])
+def test_per_call_gemms_complete_on_the_callers_stream(fmt, K):
+    """The per-call GEMMs run on an internal stream forked from the caller's
+    stream and joined back before the z-stage: waiting for the caller's stream
+    alone (a side stream of the test's own, not the null stream) must find the
+    whole translation done, eagerly and in graph replays, bit for bit equal to a
+    translation on the null stream."""
+    L = 4
+    ndir, (rk, data, comp) = _factors(fmt, K, L)
+    A_np = synth.gaussian_patterns((2, ndir) + K, 35)
+    A = torch.from_numpy(A_np).cuda()
+    ref_ctx = _ctx(no_graph=True)
+    op_r = ref_ctx.import_factors(K, L, fmt, rk, data)
+    Br = torch.zeros_like(A)
+    ref_ctx.translate(op_r, A, Br)
+    torch.cuda.synchronize()
+    ref = Br.cpu()
+    op_r.release()
+    ref_ctx.close()
+    assert O.rel_l2(ref.numpy().astype(np.complex128), O.translate_compressed(A_np, comp)) < 2e-5
+
+    ctx = _ctx(no_graph=False)
+    op = ctx.import_factors(K, L, fmt, rk, data)
+    S = torch.cuda.Stream()
+    B = torch.zeros_like(A)
+    torch.cuda.synchronize()
+    for it in range(4):  # eager + capture, then replays
+        with torch.cuda.stream(S):
+            B.zero_()
+            ctx.translate(op, A, B, stream=S)
+        S.synchronize()  # the caller's stream only
+        assert torch.equal(B.cpu(), ref), f"call {it}: result incomplete or different on the caller's stream"
     op.release()
     ctx.close()
