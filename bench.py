@@ -846,7 +846,7 @@ def _kernel_sha():
     # stored counters hold only while none of these has changed
     for f in ("api.cpp", "device_common.h", "dft_codelets.h", "gen_dft.py", "kernels.hip", "launch.h", "stages.h",
               "tucker_restore.h", "xpass.hip", "xy_stages.h", "zstage_full.hip", "zstage_tt3d.hip",
-              "zstage_tt4d.hip", "zstage_tucker.hip"):
+              "zstage_tt4d.hip", "zstage_tucker.hip", "zstage_tuckerw.hip"):
         with open(os.path.join(ROOT, "paper_2010_00520_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
